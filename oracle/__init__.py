@@ -1,0 +1,32 @@
+"""FP64 CPU oracle for one multi-reference-alignment (MRA) pass.
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test-suite, the smoke check
+in ``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import
+this package.  It shares no code with the HIP path: it never imports the
+``paper_2011_05755_amd`` package and that package never imports it.
+
+The oracle computes what the paper defines, written out plainly in NumPy
+float64 (see ``mra_oracle``): bilinear polar resampling of every shifted and
+mirrored particle, the ring-weighted rotational cross-correlation of Sec. 2 as
+a direct sum over rings and angles (no FFT), the arg-max over
+(reference, mirror, shift, angle) of Algorithm 1, and the class-average update
+of Algorithm 1 ("compute new Y' from aligned images").
+"""
+
+from .mra_oracle import (  # noqa: F401
+    Geometry,
+    align,
+    averages,
+    bilinear,
+    candidate_cc,
+    cc_table,
+    centre,
+    flat_index,
+    particle_polar,
+    polar_positions,
+    polar_samples,
+    reference_polar,
+    ring_radii,
+    ring_weights,
+    rolled_reference_matrix,
+)
