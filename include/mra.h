@@ -1,0 +1,175 @@
+/*
+ * mra.h -- C ABI of libmra.so: one multi-reference-alignment (MRA) pass of
+ * 2-D classification on an AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the problem statement of Algorithm 1 ("GPU Accelerated
+ * MRA"): input a set of particle images X and a set of reference images Y;
+ * output the class averages Y' and the alignment parameters of every image.
+ * The similarity is the ring-weighted rotational cross-correlation of Sec. 2,
+ *     c(phi) = int_{r1}^{r2} int_0^{2 pi} x(r, theta) y(r, theta + phi) |r| dtheta dr,
+ * evaluated on a polar grid (re-sample to polar coordinates, Sec. 2) for
+ * every integer shift in the search range and for the mirrored image, via
+ * FFT(x)' x FFT(y) per ring followed by an inverse FFT over angle (Sec. 3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Images are float32, row-major [L][L]; pixel (x = column, y = row) has
+ *    its centre at integer coordinates; the sampling centre is
+ *    (floor(L/2), floor(L/2)); the image is zero outside [0, L-1]^2.
+ *  - Rings r = r_min..r_max carry weight w_r = r (the |r| of the integral);
+ *    angles theta_j = 2 pi j / n_phi run from +x towards +y.
+ *  - CC[k, s, m, a] = sum_r w_r sum_j p_{s,m}[r][j] * qhat_k[r][(j + a) mod n_phi],
+ *    p_{s,m} the bilinear polar samples of the particle at centre + s
+ *    (mirror m: samples taken at angle -theta_j), qhat_k the reference's
+ *    samples divided by their weighted ring norm when normalize = 1.
+ *  - The winner maximises CC over (k, m, s, a); on exact ties the smallest
+ *    flat index  iota = (((k*M + m)*(2T+1) + (sy+T))*(2T+1) + (sx+T))*n_phi + a
+ *    wins (M = 2 with mirror search, else 1).  The reported in-plane angle is
+ *    psi = (n_phi - a) mod n_phi, so particle ~ Shift_s o Mirror^m o Rot(psi*2pi/n_phi)(ref).
+ *
+ * Memory, streams, errors
+ * -----------------------
+ *  - Every array pointer is a DEVICE pointer (e.g. torch tensor.data_ptr()).
+ *    The caller owns inputs and outputs and keeps them alive until the work
+ *    has completed; the library owns copies of loaded references and its
+ *    workspace.
+ *  - Calls are asynchronous on the stream given to mra_create; results are
+ *    valid after the caller synchronises that stream (or an event recorded
+ *    on it).  mra_load_refs is the exception: it synchronises the stream
+ *    once, to check reference norms.
+ *  - Every entry point returns MRA_OK (0) or a negative MRA_E_* code.  No C++
+ *    exception, abort or exit crosses the ABI.  When validation fails nothing
+ *    is enqueued and outputs are untouched.  After a HIP runtime error the
+ *    context is failed: every later call returns MRA_E_DEVICE until
+ *    mra_destroy.  mra_last_error() gives the context's last message.
+ *  - A context is not thread-safe; use one context per host thread.  Several
+ *    contexts may share a device and run concurrently on different streams.
+ */
+#ifndef MRA_H
+#define MRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MRA_OK = 0,
+  MRA_E_INVAL = -1,       /* bad argument or geometry                       */
+  MRA_E_NOREF = -2,       /* refset id not loaded                            */
+  MRA_E_NOMEM = -3,       /* device allocation failed or exceeds the cap     */
+  MRA_E_DEVICE = -4,      /* HIP runtime error; the context is now failed    */
+  MRA_E_DEGENERATE = -5,  /* a reference has zero weighted ring norm         */
+};
+
+enum { MRA_FP32 = 0, MRA_BF16 = 1, MRA_FP16 = 2 };
+
+typedef struct mra_ctx mra_ctx;
+
+/* Polar sampling geometry of a reference set.
+ *  L          box size, 8 <= L <= 160
+ *  r_min/max  1 <= r_min <= r_max <= 64 (integer ring radii)
+ *  n_phi      angles per ring; this build supports 256 (the paper's
+ *             workloads); other values return MRA_E_INVAL
+ *  shift_max  T >= 0: shifts {-T..T}^2 are searched (T <= 8)
+ *  mirror     1: search the mirrored image too, 0: do not
+ *  precision  MRA_FP32: FP32 correlation contraction (FP32 matrix cores);
+ *             MRA_BF16 / MRA_FP16: contraction on 16-bit matrix cores with
+ *             FP32 accumulation; polar sampling, FFTs, inverse FFTs and the
+ *             arg-max stay FP32, and the winner's CC is re-scored in FP32.
+ *  normalize  1: divide each reference by its weighted ring norm, 0: raw CC */
+typedef struct mra_geom {
+  int32_t L, r_min, r_max, n_phi, shift_max, mirror, precision, normalize;
+} mra_geom;
+
+/* Per-particle alignment parameters, structure of arrays of length N
+ * (device pointers).  cc2 and flat_index may be NULL. */
+typedef struct mra_result {
+  int32_t* ref;
+  int32_t* shift_x;
+  int32_t* shift_y;
+  int32_t* psi;
+  int32_t* mirror;
+  float* cc;
+  float* cc2;          /* optional: best CC over every other candidate      */
+  int32_t* flat_index; /* optional: iota of the winner                      */
+} mra_result;
+
+/* One stack of an uneven batch (mra_align_batch). */
+typedef struct mra_stack {
+  int32_t refset_id;
+  const float* parts;  /* [N][L][L], L of the refset                        */
+  int64_t N;
+  int32_t shift_max;   /* < 0: the refset's shift_max                       */
+  mra_result out;
+} mra_stack;
+
+/* Create a context on `device` whose work is enqueued on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  `workspace_cap_bytes` bounds the
+ * device workspace (0 = 8 GiB); large calls are split into chunks that fit. */
+int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_cap_bytes);
+
+/* Free every refset and the workspace (synchronises the stream). */
+int mra_destroy(mra_ctx* ctx);
+
+/* Reference preparation (Algorithm 1: convert y_i to polar coordinates and
+ * apply the FFT).  `refs` is float32 [K][L][L] on the device.  Samples every
+ * reference on the polar grid, takes the per-ring spectra, folds in w_r,
+ * 1/norm and the inverse-DFT scale and keeps them resident under
+ * `refset_id` (replacing an existing one).  Errors: MRA_E_INVAL (geometry or
+ * K < 1), MRA_E_DEGENERATE (zero norm with normalize = 1), MRA_E_NOMEM. */
+int mra_load_refs(mra_ctx* ctx, int32_t refset_id, const float* refs, int32_t K,
+                  const mra_geom* g);
+
+/* Free one refset.  MRA_E_NOREF if absent. */
+int mra_unload_refs(mra_ctx* ctx, int32_t refset_id);
+
+/* K and geometry of a loaded refset (host pointers). */
+int mra_refset_info(mra_ctx* ctx, int32_t refset_id, int32_t* K, mra_geom* g);
+
+/* Multi-reference alignment of N particles (Algorithm 1, inner loops and the
+ * reduction of Fig. 2): for every particle, every shift, both mirrors and
+ * every reference, the CC over all n_phi angles, then the arg-max.  `parts`
+ * is float32 [N][L][L]; `out` arrays have length N.  N = 0 is a no-op.
+ * Errors: MRA_E_NOREF, MRA_E_INVAL, MRA_E_NOMEM. */
+int mra_align(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
+              mra_result* out);
+
+/* Class-average update (Algorithm 1: apply the alignment parameters to each
+ * image, compute new Y' from the aligned images).  For each class k with
+ * n_k > 0:  Y'_k(u) = (1/n_k) sum_{ref_n = k} Bil(X_n; c + s_n + Mir^{m_n} Rot(psi_n 2pi/n_phi)(u - c)),
+ * Mir = diag(1, -1); classes with no member keep their previous image.
+ * `averages` float32 [K][L][L] is in/out (in: previous Y, out: Y'); `counts`
+ * int32 [K] receives n_k.  `params` may come from mra_align or the caller
+ * (ref, shift_x, shift_y, psi, mirror are read).  The sum over a class runs
+ * in a fixed order, so the result is deterministic. */
+int mra_update_averages(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
+                        const mra_result* params, float* averages, int32_t* counts);
+
+/* Alignment of several stacks of uneven size (each against its own refset,
+ * with its own shift range) in one call.  Each stack's results equal those
+ * of mra_align on it alone.  Errors as mra_align, checked for every stack
+ * before anything is enqueued. */
+int mra_align_batch(mra_ctx* ctx, const mra_stack* stacks, int32_t n);
+
+/* Debug exports (same kernels as the production path).
+ *  mra_debug_polar:    float32 [N][S][n_rings][n_phi] unmirrored polar
+ *                      samples, S = (2T+1)^2 shifts ordered (sy, sx).
+ *  mra_debug_spectra:  float32 [N][S][n_rings][n_phi/2 + 1][2] ring spectra
+ *                      P_f = sum_j p_j exp(-2 pi i f j / n_phi).
+ *  mra_debug_cctable:  float32 [N][K][M][2T+1][2T+1][n_phi] full CC table.
+ *  mra_debug_refs:     qhat float32 [K][n_rings][n_phi], norm float64 [K]. */
+int mra_debug_polar(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N, float* out);
+int mra_debug_spectra(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N, float* out);
+int mra_debug_cctable(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N, float* out);
+int mra_debug_refs(mra_ctx* ctx, int32_t refset_id, float* qhat, double* norm);
+
+const char* mra_last_error(mra_ctx* ctx);
+const char* mra_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRA_H */

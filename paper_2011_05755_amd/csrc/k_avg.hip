@@ -1,0 +1,164 @@
+// Class-average update (Algorithm 1: "find the corresponding alignment
+// parameters and apply them to each image", "compute new Y' from aligned
+// images").  Each particle is warped back into its reference frame,
+//   aligned(u) = Bil(X; c + s + Mir^m Rot(psi 2 pi / 256)(u - c)),
+// and summed per class.  The sum runs in a fixed order so the result does
+// not depend on scheduling:
+//   1. per block of 1024 particles, per-class counts;
+//   2. one workgroup scans them into stable class offsets and splits every
+//      class into chunks of at most kAvgChunk particles;
+//   3. particles are scattered into class order (stable);
+//   4. one workgroup per chunk stages each image in LDS (coalesced read),
+//      warps it and accumulates in FP64 registers;
+//   5. per class and pixel the chunk sums are added in chunk order and
+//      divided by the count; classes without members keep their image.
+#include "mra_common.h"
+
+namespace mra {
+
+constexpr int kAvgBlk = 1024;
+
+__global__ __launch_bounds__(256) void k_avg_hist(AvgArgs a) {
+  extern __shared__ int hist[];
+  for (int k = threadIdx.x; k < a.K; k += 256) hist[k] = 0;
+  __syncthreads();
+  const int64_t n0 = (int64_t)blockIdx.x * kAvgBlk;
+  for (int i = threadIdx.x; i < kAvgBlk; i += 256) {
+    const int64_t n = n0 + i;
+    if (n < a.N) {
+      const int k = a.ref[n];
+      if (k >= 0 && k < a.K) atomicAdd(&hist[k], 1);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.K; k += 256) a.blk_cnt[(size_t)blockIdx.x * a.K + k] = hist[k];
+}
+
+__global__ __launch_bounds__(256) void k_avg_scan(AvgArgs a) {
+  for (int k = threadIdx.x; k < a.K; k += 256) {
+    int run = 0;
+    for (int b = 0; b < a.n_blk; ++b) {
+      a.blk_off[(size_t)b * a.K + k] = run;
+      run += a.blk_cnt[(size_t)b * a.K + k];
+    }
+    a.counts[k] = run;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cs = 0, ch = 0;
+    for (int k = 0; k < a.K; ++k) {
+      a.cls_start[k] = cs;
+      a.chunk_start[k] = ch;
+      cs += a.counts[k];
+      ch += (a.counts[k] + kAvgChunk - 1) / kAvgChunk;
+    }
+    a.cls_start[a.K] = cs;
+    a.chunk_start[a.K] = ch;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.K; k += 256)
+    for (int b = 0; b < a.n_blk; ++b) a.blk_off[(size_t)b * a.K + k] += a.cls_start[k];
+}
+
+__global__ void k_avg_scatter(AvgArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.n_blk) return;
+  int* off = a.blk_off + (size_t)b * a.K;
+  const int64_t n0 = (int64_t)b * kAvgBlk;
+  for (int i = 0; i < kAvgBlk; ++i) {
+    const int64_t n = n0 + i;
+    if (n >= a.N) break;
+    const int k = a.ref[n];
+    if (k >= 0 && k < a.K) a.order[off[k]++] = (int)n;
+  }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
+  extern __shared__ float img[];
+  const int c = blockIdx.x;
+  if (c >= a.chunk_start[a.K]) return;
+  int lo = 0, hi = a.K - 1;  // largest k with chunk_start[k] <= c (classes may be empty)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.chunk_start[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int k = lo;
+  const int start = a.cls_start[k] + (c - a.chunk_start[k]) * kAvgChunk;
+  int end = start + kAvgChunk;
+  if (end > a.cls_start[k + 1]) end = a.cls_start[k + 1];
+  const int L = a.L, L2 = L * L;
+  double acc[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) acc[i] = 0.0;
+  for (int pi = start; pi < end; ++pi) {
+    const int n = a.order[pi];
+    __syncthreads();
+    const float* src = a.parts + (size_t)n * L2;
+    for (int i = threadIdx.x; i < L2; i += kAvgThreads) img[i] = src[i];
+    __syncthreads();
+    const double2 cs = a.cs64[a.psi[n] & 255];
+    const double sx = a.shift_x[n], sy = a.shift_y[n];
+    const double msign = a.mirror[n] ? -1.0 : 1.0;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int u = threadIdx.x + i * kAvgThreads;
+      if (u < L2) {
+        const double vx = (double)(u % L - a.cx), vy = (double)(u / L - a.cx);
+        const double rx = cs.x * vx - cs.y * vy;
+        const double ry = msign * (cs.y * vx + cs.x * vy);
+        const double X = a.cx + sx + rx, Y = a.cx + sy + ry;
+        const double x0 = floor(X), y0 = floor(Y);
+        const float fx = (float)(X - x0), fy = (float)(Y - y0);
+        const int ix = (int)x0, iy = (int)y0;
+        const bool in_x0 = ix >= 0 && ix < L, in_x1 = ix + 1 >= 0 && ix + 1 < L;
+        const bool in_y0 = iy >= 0 && iy < L, in_y1 = iy + 1 >= 0 && iy + 1 < L;
+        const float i00 = (in_x0 && in_y0) ? img[iy * L + ix] : 0.f;
+        const float i10 = (in_x1 && in_y0) ? img[iy * L + ix + 1] : 0.f;
+        const float i01 = (in_x0 && in_y1) ? img[(iy + 1) * L + ix] : 0.f;
+        const float i11 = (in_x1 && in_y1) ? img[(iy + 1) * L + ix + 1] : 0.f;
+        const float top = i00 + fx * (i10 - i00);
+        const float bot = i01 + fx * (i11 - i01);
+        acc[i] += (double)(top + fy * (bot - top));
+      }
+    }
+  }
+  float* out = a.partial + (size_t)c * L2;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int u = threadIdx.x + i * kAvgThreads;
+    if (u < L2) out[u] = (float)acc[i];
+  }
+}
+
+__global__ void k_avg_final(AvgArgs a) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int L2 = a.L * a.L;
+  if (i >= (int64_t)a.K * L2) return;
+  const int k = i / L2, u = i % L2;
+  const int cnt = a.counts[k];
+  if (cnt == 0) return;
+  double s = 0.0;
+  for (int c = a.chunk_start[k]; c < a.chunk_start[k + 1]; ++c) s += a.partial[(size_t)c * L2 + u];
+  a.averages[i] = (float)(s / cnt);
+}
+
+hipError_t launch_averages(const AvgArgs& a, hipStream_t st) {
+  if (a.N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_avg_hist, dim3(a.n_blk), dim3(256), (size_t)a.K * sizeof(int), st, a);
+  hipLaunchKernelGGL(k_avg_scan, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_avg_scatter, dim3((a.n_blk + 63) / 64), dim3(64), 0, st, a);
+  const int L2 = a.L * a.L;
+  const size_t lds = (size_t)L2 * sizeof(float);
+  const int ppt = (L2 + kAvgThreads - 1) / kAvgThreads;
+  dim3 g(a.max_chunks), b(kAvgThreads);
+  if (ppt <= 16) hipLaunchKernelGGL(k_avg_accum<16>, g, b, lds, st, a);
+  else if (ppt <= 32) hipLaunchKernelGGL(k_avg_accum<32>, g, b, lds, st, a);
+  else if (ppt <= 64) hipLaunchKernelGGL(k_avg_accum<64>, g, b, lds, st, a);
+  else hipLaunchKernelGGL(k_avg_accum<100>, g, b, lds, st, a);
+  const int64_t nf = (int64_t)a.K * L2;
+  hipLaunchKernelGGL(k_avg_final, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace mra

@@ -1,0 +1,216 @@
+// Shift + polar resampling and per-ring FFT of particle images (Algorithm 1:
+// "convert x_i to polar coordinates with given shift and apply FFT"), the
+// FP32 re-score of a winning candidate, and a max-|x| reduction.
+//
+// One workgroup per particle.  The image is staged once in LDS with a zero
+// border (coalesced HBM read), then every wave takes one ring at a time for
+// eight shifts at once: lane (l, row) holds the 32 samples p[16 n1 + 2l + e]
+// of shift `row`, whose bilinear stencils stay in registers for all shifts
+// (integer shifts move the stencil by whole pixels).  The 256-point real FFT
+// runs as a 16 x 8 complex FFT across the eight lanes l of a shift with one
+// transpose through a per-wave LDS scratch.
+#include "mra_common.h"
+#include "mra_fft.h"
+
+namespace mra {
+
+__device__ __forceinline__ float2 w256f(const float2* cs, int e) {
+  float2 c = cs[e & 255];
+  return make_float2(c.x, -c.y);  // exp(-2 pi i e / 256)
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void stage_image(float* img, const float* src, int L, int Lp, int pad) {
+  for (int i = threadIdx.x; i < Lp * Lp; i += blockDim.x) {
+    const int yy = i / Lp - pad, xx = i % Lp - pad;
+    img[i] = (yy >= 0 && yy < L && xx >= 0 && xx < L) ? src[yy * L + xx] : 0.f;
+  }
+}
+
+__device__ __forceinline__ float bilin(const float* img, int o, int Lp, float fx, float fy) {
+  const float i00 = img[o], i10 = img[o + 1], i01 = img[o + Lp], i11 = img[o + Lp + 1];
+  const float top = i00 + fx * (i10 - i00);
+  const float bot = i01 + fx * (i11 - i01);
+  return top + fy * (bot - top);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
+  extern __shared__ float smem[];
+  float* img = smem;
+  float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
+  const int n = blockIdx.x;
+  stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
+  __syncthreads();
+
+  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int l = ln >> 3, rl = ln & 7;
+  float2* my = scr + w * 64 * 17;
+  int k1a, k1b;
+  fwd_cols(l, k1a, k1b);
+  const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
+  const int ngrp = (a.S + 7) >> 3;
+
+  for (int ring = w; ring < a.R; ring += 8) {
+    int off[32];
+    float fx[32], fy[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const Stencil s = a.stencil[ring * kNphi + 16 * (i >> 1) + 2 * l + (i & 1)];
+      off[i] = base + s.dy * a.Lp + s.dx;
+      fx[i] = s.fx;
+      fy[i] = s.fy;
+    }
+    for (int grp = 0; grp < ngrp; ++grp) {
+      const int s = grp * 8 + rl;
+      const bool valid = s < a.S;
+      const int sc = valid ? s : a.S - 1;
+      const int soff = (sc / a.S1 - a.T) * a.Lp + (sc % a.S1 - a.T);
+      float v[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = bilin(img, off[i] + soff, a.Lp, fx[i], fy[i]);
+
+      if (MODE == 1) {
+        if (valid) {
+          float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * kNphi;
+#pragma unroll
+          for (int i = 0; i < 32; ++i) o[16 * (i >> 1) + 2 * l + (i & 1)] = v[i];
+        }
+        continue;
+      }
+
+      float2 z[16];
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
+      dft16<-1>(z);
+#pragma unroll
+      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], w256f(a.cs32, 2 * ((l * k1) & 127)));
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) my[(rl * 8 + l) * 17 + k1] = z[k1];
+      wave_sync();
+      float2 Za[8], Zb[8];
+#pragma unroll
+      for (int n2 = 0; n2 < 8; ++n2) {
+        Za[n2] = my[(rl * 8 + n2) * 17 + k1a];
+        Zb[n2] = my[(rl * 8 + n2) * 17 + k1b];
+      }
+      wave_sync();
+      dft8<-1>(Za);
+      dft8<-1>(Zb);
+
+      if (MODE == 0) {
+        const int row = n * a.S + s;
+        const int g = ring / a.R4, t = ring - g * a.R4;
+        float* o = a.out + (size_t)(row >> 3) * kSlots * a.R4 * 64 + t * 64 + g * 16 + (row & 7);
+        const size_t slot_stride = (size_t)a.R4 * 64;
+        fwd_emit(l, Za, Zb, [&](int f) { return w256f(a.cs32, f); },
+                 [&](int slot, float re, float im) {
+                   if (!valid) return;
+                   o[slot * slot_stride] = re - im;
+                   o[slot * slot_stride + 8] = re + im;
+                 });
+      } else {  // MODE 2: plain spectra
+        float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * 129 * 2;
+        fwd_emit(l, Za, Zb, [&](int f) { return w256f(a.cs32, f); },
+                 [&](int slot, float re, float im) {
+                   if (!valid) return;
+                   if (slot == 0) {
+                     o[0] = re; o[1] = 0.f;
+                     o[256] = im; o[257] = 0.f;
+                   } else {
+                     o[2 * slot] = re;
+                     o[2 * slot + 1] = im;
+                   }
+                 });
+      }
+    }
+  }
+}
+
+size_t polar_lds_bytes(int Lp) {
+  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)8 * 64 * 17 * sizeof(float2);
+}
+
+hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
+  if (a.n_part <= 0) return hipSuccess;
+  const size_t lds = polar_lds_bytes(a.Lp);
+  dim3 grid(a.n_part), block(kPolarThreads);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(k_polar_fft<0>, grid, block, lds, st, a); break;
+    case 1: hipLaunchKernelGGL(k_polar_fft<1>, grid, block, lds, st, a); break;
+    default: hipLaunchKernelGGL(k_polar_fft<2>, grid, block, lds, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+// FP32 re-score of each particle's winner: the direct double sum
+// sum_r w_r sum_j p_{s,m}[r][j] * qhat_k[r][(j + a) mod 256] with a = -psi.
+// The mirrored samples are the unmirrored stencil read at angle -j (the
+// stencil table is built symmetric in j <-> 256 - j).
+__global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
+  extern __shared__ float smem[];
+  float* img = smem;
+  __shared__ double red[256];
+  const int n = blockIdx.x;
+  const int64_t gi = a.out_off + n;
+  stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
+  __syncthreads();
+  const int k = a.ref[gi], m = a.mirror[gi] ? 1 : 0;
+  const int sx = a.shift_x[gi], sy = a.shift_y[gi];
+  if (k < 0 || k >= a.K || sx < -a.T || sx > a.T || sy < -a.T || sy > a.T) {
+    if (threadIdx.x == 0) a.cc[gi] = NAN;
+    return;  // uniform over the block
+  }
+  const int lag = (kNphi - a.psi[gi]) & 255;
+  const int soff = sy * a.Lp + sx;
+  const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
+  const int j = threadIdx.x;
+  const int jj = m ? ((kNphi - j) & 255) : j;
+  const float* q = a.qhat + (size_t)k * a.R * kNphi;
+  float acc = 0.f;
+  for (int r = 0; r < a.R; ++r) {
+    const Stencil s = a.stencil[r * kNphi + jj];
+    const float p = bilin(img, base + s.dy * a.Lp + s.dx + soff, a.Lp, s.fx, s.fy);
+    acc += (float)(a.r_min + r) * (p * q[r * kNphi + ((j + lag) & 255)]);
+  }
+  red[j] = (double)acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (j < h) red[j] += red[j + h];
+    __syncthreads();
+  }
+  if (j == 0) a.cc[gi] = (float)red[0];
+}
+
+hipError_t launch_rescore(const RescoreArgs& a, hipStream_t st) {
+  if (a.n_part <= 0) return hipSuccess;
+  const size_t lds = (size_t)a.Lp * a.Lp * sizeof(float);
+  hipLaunchKernelGGL(k_rescore, dim3(a.n_part), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+// max |x| over n floats into *out (which the caller zeroes); non-negative
+// floats order like their bit patterns, so an integer atomic max suffices.
+__global__ __launch_bounds__(256) void k_maxabs(const float* x, int64_t n, float* out) {
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(x[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(m));
+}
+
+hipError_t launch_maxabs(const float* x, int64_t n, float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_maxabs, dim3(blocks), dim3(256), 0, st, x, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace mra

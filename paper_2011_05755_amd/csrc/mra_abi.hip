@@ -1,0 +1,557 @@
+// Host side of libmra.so: contexts, resident reference sets, validation,
+// chunk planning and the launch sequence of one MRA pass (Algorithm 1).
+// Every entry point is extern "C", catches everything, and reports through
+// an int status plus a per-context message (see include/mra.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mra.h"
+#include "mra_common.h"
+
+using namespace mra;
+
+namespace {
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Refset {
+  mra_geom g{};
+  int K = 0, R = 0, R4 = 0, NS = 0, n_kt = 0;
+  float* B32 = nullptr;
+  uint16_t* B16 = nullptr;
+  float* qhat = nullptr;
+  double* norm = nullptr;
+  Stencil* stencil = nullptr;
+  float b_scale = 1.f;
+  int dmin = 0, dmax = 0;  // range of stencil floor offsets
+};
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+}  // namespace
+
+struct mra_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t cap = 0;
+  bool failed = false;
+  std::string err;
+  std::map<int32_t, Refset> refs;
+  double2* cs64 = nullptr;
+  float2* cs32 = nullptr;
+  std::map<std::string, DevBuf> ws;
+};
+
+namespace {
+
+void hip_check(mra_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    c->failed = true;
+    throw Fail{MRA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+  }
+}
+
+void* alloc(mra_ctx* c, size_t bytes, const char* what) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes < 16 ? 16 : bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    throw Fail{MRA_E_NOMEM, std::string("out of device memory allocating ") + what};
+  }
+  hip_check(c, e, what);
+  return p;
+}
+
+void* ws_get(mra_ctx* c, const std::string& name, size_t bytes) {
+  DevBuf& b = c->ws[name];
+  if (b.bytes < bytes) {
+    if (b.p) hip_check(c, hipFree(b.p), "hipFree");
+    b.p = nullptr;
+    b.bytes = 0;
+    b.p = alloc(c, bytes, name.c_str());
+    b.bytes = bytes;
+  }
+  return b.p;
+}
+
+void free_refset(Refset& r) {
+  for (void* p : {(void*)r.B32, (void*)r.B16, (void*)r.qhat, (void*)r.norm, (void*)r.stencil})
+    if (p) (void)hipFree(p);
+  r = Refset{};
+}
+
+// cos / sin of 2 pi j / n built from the first octant so that the table is
+// exactly symmetric (cos even, sin odd, quarter turns exact).
+void build_cs(int n, std::vector<double>& c, std::vector<double>& s) {
+  c.assign(n, 0.0);
+  s.assign(n, 0.0);
+  const double two_pi = 6.283185307179586476925286766559;
+  const int q = n / 4, e = n / 8;
+  std::vector<double> c0(q + 1), s0(q + 1);
+  for (int j = 0; j <= e; ++j) {
+    c0[j] = std::cos(two_pi * j / n);
+    s0[j] = std::sin(two_pi * j / n);
+  }
+  for (int j = e + 1; j <= q; ++j) {
+    c0[j] = s0[q - j];
+    s0[j] = c0[q - j];
+  }
+  for (int j = 0; j < n; ++j) {
+    int jj = j, sc = 1, ss = 1;
+    if (jj > n / 2) { jj = n - jj; ss = -1; }          // theta -> -theta
+    if (jj > q) { jj = n / 2 - jj; sc = -1; }          // theta -> pi - theta
+    c[j] = sc * c0[jj];
+    s[j] = ss * s0[jj];
+  }
+}
+
+void check_geom(const mra_geom* g) {
+  auto bad = [](const char* m) { throw Fail{MRA_E_INVAL, m}; };
+  if (!g) bad("geometry is NULL");
+  if (g->L < 8 || g->L > 160) bad("L must be in [8, 160]");
+  if (g->r_min < 1 || g->r_max < g->r_min || g->r_max > 64) bad("need 1 <= r_min <= r_max <= 64");
+  if (g->n_phi != kNphi) bad("n_phi must be 256 in this build");
+  if (g->shift_max < 0 || g->shift_max > 8) bad("shift_max must be in [0, 8]");
+  if (g->mirror != 0 && g->mirror != 1) bad("mirror must be 0 or 1");
+  if (g->precision < 0 || g->precision > 2) bad("precision must be MRA_FP32, MRA_BF16 or MRA_FP16");
+  if (g->normalize != 0 && g->normalize != 1) bad("normalize must be 0 or 1");
+}
+
+Refset& get_refset(mra_ctx* c, int32_t id) {
+  auto it = c->refs.find(id);
+  if (it == c->refs.end()) throw Fail{MRA_E_NOREF, "refset " + std::to_string(id) + " is not loaded"};
+  return it->second;
+}
+
+struct Plan {
+  int T, S1, S, M, pad, Lp, cx;
+};
+
+Plan plan_for(const Refset& rs, int T) {
+  if (T < 0 || T > 8) throw Fail{MRA_E_INVAL, "shift_max must be in [0, 8]"};
+  Plan p;
+  p.T = T;
+  p.S1 = 2 * T + 1;
+  p.S = p.S1 * p.S1;
+  p.M = rs.g.mirror ? 2 : 1;
+  p.cx = rs.g.L / 2;
+  const int lo = p.cx - T + rs.dmin;          // lowest pixel index touched
+  const int hi = p.cx + T + rs.dmax + 1;      // highest
+  p.pad = std::max(0, std::max(-lo, hi - (rs.g.L - 1)));
+  p.Lp = rs.g.L + 2 * p.pad;
+  if (polar_lds_bytes(p.Lp) > kLdsMax)
+    throw Fail{MRA_E_INVAL, "box plus search range too large for the LDS-staged resampler"};
+  return p;
+}
+
+void check_result(const mra_result* r) {
+  if (!r || !r->ref || !r->shift_x || !r->shift_y || !r->psi || !r->mirror || !r->cc)
+    throw Fail{MRA_E_INVAL, "result arrays must be non-NULL (cc2, flat_index may be NULL)"};
+}
+
+// bytes of the correlation operand A per particle row (one eighth of a tile)
+size_t a_bytes_per_row(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * sizeof(float) / kRowTile; }
+
+int64_t chunk_particles(mra_ctx* c, const Refset& rs, const Plan& p) {
+  const uint64_t budget = std::max<uint64_t>(c->cap / 2, 64ull << 20);
+  const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
+  int64_t n = (int64_t)(budget / per);
+  return std::max<int64_t>(n, 1);
+}
+
+// One chunk of the alignment pass: resample + FFT -> correlation -> merge
+// (-> FP32 re-score for 16-bit contractions).  mode 0 = production,
+// mode 3 = debug CC table into `table`.
+void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, int64_t n0, int nc,
+               const mra_result* out, float* table) {
+  hipStream_t st = c->stream;
+  const int L = rs.g.L;
+  const int rows = nc * p.S;
+  const int tiles = (rows + kRowTile - 1) / kRowTile;
+  const size_t tile_bytes = (size_t)kSlots * rs.R4 * 64 * sizeof(float);
+  float* A = (float*)ws_get(c, "A", (size_t)tiles * tile_bytes);
+  float* rcc = (float*)ws_get(c, "row_cc", (size_t)rows * sizeof(float));
+  int* ridx = (int*)ws_get(c, "row_idx", (size_t)rows * sizeof(int));
+  if (rows % kRowTile) hip_check(c, hipMemsetAsync(A + (size_t)(tiles - 1) * tile_bytes / sizeof(float), 0, tile_bytes, st), "memset");
+  const float* src = parts + (size_t)n0 * L * L;
+
+  float* maxabs = nullptr;
+  if (rs.g.precision == kFP16) {
+    maxabs = (float*)ws_get(c, "maxabs", 256);
+    hip_check(c, hipMemsetAsync(maxabs, 0, sizeof(float), st), "memset");
+    hip_check(c, launch_maxabs(src, (int64_t)nc * L * L, maxabs, st), "maxabs");
+  }
+
+  PolarArgs pa{};
+  pa.parts = src;
+  pa.n_part = nc;
+  pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
+  pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx;
+  pa.stencil = rs.stencil;
+  pa.cs32 = c->cs32;
+  pa.out = A;
+  hip_check(c, launch_polar(0, pa, st), "polar");
+
+  CorrArgs ca{};
+  ca.A = A;
+  ca.n_row_tiles = tiles;
+  ca.rows = rows;
+  ca.B32 = rs.B32;
+  ca.B16 = rs.B16;
+  ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = p.S; ca.M = p.M;
+  ca.maxabs = maxabs;
+  ca.b_scale = rs.b_scale;
+  ca.cs32 = c->cs32;
+  ca.row_cc = rcc;
+  ca.row_idx = ridx;
+  ca.table = table;
+  hip_check(c, launch_corr(rs.g.precision, table != nullptr, ca, st), "corr");
+  if (table) return;
+
+  MergeArgs ma{};
+  ma.row_cc = rcc; ma.row_idx = ridx;
+  ma.n_part = nc; ma.S = p.S; ma.S1 = p.S1; ma.T = p.T; ma.M = p.M;
+  ma.out_off = n0;
+  ma.ref = out->ref; ma.shift_x = out->shift_x; ma.shift_y = out->shift_y;
+  ma.psi = out->psi; ma.mirror = out->mirror; ma.flat = out->flat_index;
+  ma.cc = out->cc; ma.cc2 = out->cc2;
+  hip_check(c, launch_merge(ma, st), "merge");
+
+  if (rs.g.precision != kFP32) {
+    RescoreArgs ra{};
+    ra.parts = src;
+    ra.n_part = nc;
+    ra.out_off = n0;
+    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx;
+    ra.K = rs.K; ra.T = p.T;
+    ra.stencil = rs.stencil;
+    ra.qhat = rs.qhat;
+    ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
+    ra.psi = out->psi; ra.mirror = out->mirror;
+    ra.cc = out->cc;
+    hip_check(c, launch_rescore(ra, st), "rescore");
+  }
+}
+
+void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, const mra_result* out,
+                float* table) {
+  Refset& rs = get_refset(c, id);
+  if (N < 0) throw Fail{MRA_E_INVAL, "N must be >= 0"};
+  if (N == 0) return;
+  if (!parts) throw Fail{MRA_E_INVAL, "parts is NULL"};
+  if (!table) check_result(out);
+  const Plan p = plan_for(rs, T < 0 ? rs.g.shift_max : T);
+  const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
+  for (int64_t n0 = 0; n0 < N; n0 += step) {
+    const int nc = (int)std::min<int64_t>(step, N - n0);
+    float* tab = table ? table + (size_t)n0 * rs.K * p.M * p.S * kNphi : nullptr;
+    run_chunk(c, rs, p, parts, n0, nc, out, tab);
+  }
+}
+
+template <class F>
+int guard(mra_ctx* c, F&& fn) {
+  if (!c) return MRA_E_INVAL;
+  if (c->failed) {
+    c->err = "context failed after an earlier device error";
+    return MRA_E_DEVICE;
+  }
+  try {
+    hip_check(c, hipSetDevice(c->device), "hipSetDevice");
+    fn();
+    return MRA_OK;
+  } catch (const Fail& f) {
+    c->err = f.msg;
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host out of memory";
+    return MRA_E_NOMEM;
+  } catch (...) {
+    c->err = "unexpected internal error";
+    return MRA_E_INVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_cap_bytes) {
+  if (!out) return MRA_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return MRA_E_INVAL;
+  }
+  mra_ctx* c = new (std::nothrow) mra_ctx;
+  if (!c) return MRA_E_NOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->cap = workspace_cap_bytes ? workspace_cap_bytes : (8ull << 30);
+  int rc = guard(c, [&] {
+    std::vector<double> cs, sn;
+    build_cs(kNphi, cs, sn);
+    std::vector<double2> h64(kNphi);
+    std::vector<float2> h32(kNphi);
+    for (int j = 0; j < kNphi; ++j) {
+      h64[j] = make_double2(cs[j], sn[j]);
+      h32[j] = make_float2((float)cs[j], (float)sn[j]);
+    }
+    c->cs64 = (double2*)alloc(c, kNphi * sizeof(double2), "cs64");
+    c->cs32 = (float2*)alloc(c, kNphi * sizeof(float2), "cs32");
+    hip_check(c, hipMemcpy(c->cs64, h64.data(), kNphi * sizeof(double2), hipMemcpyHostToDevice), "memcpy");
+    hip_check(c, hipMemcpy(c->cs32, h32.data(), kNphi * sizeof(float2), hipMemcpyHostToDevice), "memcpy");
+  });
+  if (rc != MRA_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return MRA_OK;
+}
+
+int mra_destroy(mra_ctx* c) {
+  if (!c) return MRA_E_INVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->refs) free_refset(kv.second);
+  for (auto& kv : c->ws)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (c->cs64) (void)hipFree(c->cs64);
+  if (c->cs32) (void)hipFree(c->cs32);
+  delete c;
+  return MRA_OK;
+}
+
+int mra_load_refs(mra_ctx* c, int32_t id, const float* refs, int32_t K, const mra_geom* g) {
+  return guard(c, [&] {
+    check_geom(g);
+    if (K < 1) throw Fail{MRA_E_INVAL, "K must be >= 1"};
+    if (!refs) throw Fail{MRA_E_INVAL, "refs is NULL"};
+    Refset rs;
+    rs.g = *g;
+    rs.K = K;
+    rs.R = g->r_max - g->r_min + 1;
+    rs.R4 = (rs.R + 3) / 4;
+    rs.NS = (rs.R4 + 7) / 8;
+    rs.n_kt = (K + kRefTile - 1) / kRefTile;
+    hipStream_t st = c->stream;
+    try {
+      // particle sampling stencil, exactly symmetric in j <-> 256 - j
+      std::vector<double> cs, sn;
+      build_cs(kNphi, cs, sn);
+      std::vector<Stencil> sten((size_t)rs.R * kNphi);
+      rs.dmin = 0;
+      rs.dmax = 0;
+      for (int r = 0; r < rs.R; ++r)
+        for (int j = 0; j < kNphi; ++j) {
+          const double rr = g->r_min + r;
+          const double x = rr * cs[j], y = rr * sn[j];
+          const double fx = std::floor(x), fy = std::floor(y);
+          Stencil s;
+          s.dx = (int)fx;
+          s.dy = (int)fy;
+          s.fx = (float)(x - fx);
+          s.fy = (float)(y - fy);
+          sten[(size_t)r * kNphi + j] = s;
+          rs.dmin = std::min({rs.dmin, s.dx, s.dy});
+          rs.dmax = std::max({rs.dmax, s.dx, s.dy});
+        }
+      rs.stencil = (Stencil*)alloc(c, sten.size() * sizeof(Stencil), "stencil");
+      hip_check(c, hipMemcpyAsync(rs.stencil, sten.data(), sten.size() * sizeof(Stencil), hipMemcpyHostToDevice, st), "memcpy");
+
+      RefArgs ra{};
+      ra.refs = refs;
+      ra.K = K; ra.L = g->L; ra.r_min = g->r_min; ra.R = rs.R; ra.R4 = rs.R4; ra.NS = rs.NS;
+      ra.n_ref_tiles = rs.n_kt; ra.normalize = g->normalize; ra.prec = g->precision;
+      ra.cs64 = c->cs64;
+      ra.q64 = (double*)ws_get(c, "ref_q64", (size_t)K * rs.R * kNphi * sizeof(double));
+      ra.inv = (double*)ws_get(c, "ref_inv", (size_t)K * sizeof(double));
+      ra.Qs = (double2*)ws_get(c, "ref_Qs", (size_t)K * 129 * rs.R * sizeof(double2));
+      ra.bmax = (float*)ws_get(c, "ref_bmax", 256);
+      rs.norm = (double*)alloc(c, (size_t)K * sizeof(double), "norm");
+      rs.qhat = (float*)alloc(c, (size_t)K * rs.R * kNphi * sizeof(float), "qhat");
+      ra.norm = rs.norm;
+      ra.qhat32 = rs.qhat;
+      hip_check(c, hipMemsetAsync(ra.bmax, 0, sizeof(float), st), "memset");
+      hip_check(c, launch_ref_stage1(ra, st), "ref stage 1");
+      std::vector<double> norms(K);
+      float bmax = 0.f;
+      hip_check(c, hipMemcpyAsync(norms.data(), rs.norm, K * sizeof(double), hipMemcpyDeviceToHost, st), "memcpy");
+      hip_check(c, hipMemcpyAsync(&bmax, ra.bmax, sizeof(float), hipMemcpyDeviceToHost, st), "memcpy");
+      hip_check(c, hipStreamSynchronize(st), "sync");
+      if (g->normalize)
+        for (int k = 0; k < K; ++k)
+          if (!(norms[k] > 0.0))
+            throw Fail{MRA_E_DEGENERATE, "reference " + std::to_string(k) + " has zero weighted ring norm"};
+      rs.b_scale = 1.f;
+      if (g->precision == kFP16 && bmax > 0.f) rs.b_scale = std::ldexp(1.f, 14 - (int)std::ceil(std::log2(bmax)));
+      ra.b_scale = rs.b_scale;
+      if (g->precision == kFP32)
+        rs.B32 = (float*)alloc(c, (size_t)rs.n_kt * kSlots * rs.R4 * 64 * sizeof(float), "B32");
+      else
+        rs.B16 = (uint16_t*)alloc(c, (size_t)rs.n_kt * kSlots * rs.NS * 64 * 8 * sizeof(uint16_t), "B16");
+      ra.B32 = rs.B32;
+      ra.B16 = rs.B16;
+      hip_check(c, launch_ref_stage2(ra, st), "ref stage 2");
+    } catch (...) {
+      free_refset(rs);
+      throw;
+    }
+    auto it = c->refs.find(id);
+    if (it != c->refs.end()) {
+      hip_check(c, hipStreamSynchronize(st), "sync");
+      free_refset(it->second);
+      c->refs.erase(it);
+    }
+    c->refs[id] = rs;
+  });
+}
+
+int mra_unload_refs(mra_ctx* c, int32_t id) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    free_refset(rs);
+    c->refs.erase(id);
+  });
+}
+
+int mra_refset_info(mra_ctx* c, int32_t id, int32_t* K, mra_geom* g) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (K) *K = rs.K;
+    if (g) *g = rs.g;
+  });
+}
+
+int mra_align(mra_ctx* c, int32_t id, const float* parts, int64_t N, mra_result* out) {
+  return guard(c, [&] { align_impl(c, id, parts, N, -1, out, nullptr); });
+}
+
+int mra_align_batch(mra_ctx* c, const mra_stack* stacks, int32_t n) {
+  return guard(c, [&] {
+    if (n < 0 || (n > 0 && !stacks)) throw Fail{MRA_E_INVAL, "bad stack list"};
+    for (int i = 0; i < n; ++i) {  // validate everything before enqueueing anything
+      const mra_stack& s = stacks[i];
+      Refset& rs = get_refset(c, s.refset_id);
+      if (s.N < 0) throw Fail{MRA_E_INVAL, "stack N must be >= 0"};
+      if (s.N > 0) {
+        if (!s.parts) throw Fail{MRA_E_INVAL, "stack parts is NULL"};
+        check_result(&s.out);
+        plan_for(rs, s.shift_max < 0 ? rs.g.shift_max : s.shift_max);
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      align_impl(c, stacks[i].refset_id, stacks[i].parts, stacks[i].N, stacks[i].shift_max, &stacks[i].out, nullptr);
+  });
+}
+
+int mra_update_averages(mra_ctx* c, int32_t id, const float* parts, int64_t N, const mra_result* params,
+                        float* averages, int32_t* counts) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (N < 0 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
+    if (!averages || !counts) throw Fail{MRA_E_INVAL, "averages and counts must be non-NULL"};
+    if (!params || !params->ref || !params->shift_x || !params->shift_y || !params->psi || !params->mirror)
+      throw Fail{MRA_E_INVAL, "params arrays must be non-NULL"};
+    if (N > 0 && !parts) throw Fail{MRA_E_INVAL, "parts is NULL"};
+    hipStream_t st = c->stream;
+    const int K = rs.K, L = rs.g.L;
+    if (N == 0) {
+      hip_check(c, hipMemsetAsync(counts, 0, K * sizeof(int32_t), st), "memset");
+      return;
+    }
+    AvgArgs a{};
+    a.parts = parts;
+    a.N = N;
+    a.K = K; a.L = L; a.cx = L / 2;
+    a.ref = params->ref; a.shift_x = params->shift_x; a.shift_y = params->shift_y;
+    a.psi = params->psi; a.mirror = params->mirror;
+    a.cs64 = c->cs64;
+    a.n_blk = (int)((N + 1023) / 1024);
+    a.max_chunks = (int)((N + kAvgChunk - 1) / kAvgChunk) + K;
+    a.blk_cnt = (int*)ws_get(c, "avg_blk_cnt", (size_t)a.n_blk * K * sizeof(int));
+    a.blk_off = (int*)ws_get(c, "avg_blk_off", (size_t)a.n_blk * K * sizeof(int));
+    a.cls_start = (int*)ws_get(c, "avg_cls", (size_t)(K + 1) * sizeof(int));
+    a.chunk_start = (int*)ws_get(c, "avg_chunk", (size_t)(K + 1) * sizeof(int));
+    a.order = (int*)ws_get(c, "avg_order", (size_t)N * sizeof(int));
+    a.partial = (float*)ws_get(c, "avg_partial", (size_t)a.max_chunks * L * L * sizeof(float));
+    a.averages = averages;
+    a.counts = counts;
+    hip_check(c, launch_averages(a, st), "averages");
+  });
+}
+
+int mra_debug_polar(mra_ctx* c, int32_t id, const float* parts, int64_t N, float* out) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (N < 0 || N > INT32_MAX || (N > 0 && (!parts || !out))) throw Fail{MRA_E_INVAL, "bad arguments"};
+    const Plan p = plan_for(rs, rs.g.shift_max);
+    PolarArgs pa{};
+    pa.parts = parts; pa.n_part = (int)N;
+    pa.L = rs.g.L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
+    pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx; pa.stencil = rs.stencil; pa.cs32 = c->cs32; pa.out = out;
+    hip_check(c, launch_polar(1, pa, c->stream), "polar");
+  });
+}
+
+int mra_debug_spectra(mra_ctx* c, int32_t id, const float* parts, int64_t N, float* out) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (N < 0 || N > INT32_MAX || (N > 0 && (!parts || !out))) throw Fail{MRA_E_INVAL, "bad arguments"};
+    const Plan p = plan_for(rs, rs.g.shift_max);
+    PolarArgs pa{};
+    pa.parts = parts; pa.n_part = (int)N;
+    pa.L = rs.g.L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
+    pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx; pa.stencil = rs.stencil; pa.cs32 = c->cs32; pa.out = out;
+    hip_check(c, launch_polar(2, pa, c->stream), "polar");
+  });
+}
+
+int mra_debug_cctable(mra_ctx* c, int32_t id, const float* parts, int64_t N, float* out) {
+  return guard(c, [&] {
+    if (N > 0 && !out) throw Fail{MRA_E_INVAL, "out is NULL"};
+    align_impl(c, id, parts, N, -1, nullptr, out);
+  });
+}
+
+int mra_debug_refs(mra_ctx* c, int32_t id, float* qhat, double* norm) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (qhat)
+      hip_check(c, hipMemcpyAsync(qhat, rs.qhat, (size_t)rs.K * rs.R * kNphi * sizeof(float), hipMemcpyDeviceToDevice, c->stream), "memcpy");
+    if (norm)
+      hip_check(c, hipMemcpyAsync(norm, rs.norm, (size_t)rs.K * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "memcpy");
+  });
+}
+
+const char* mra_last_error(mra_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+const char* mra_strerror(int code) {
+  switch (code) {
+    case MRA_OK: return "ok";
+    case MRA_E_INVAL: return "invalid argument";
+    case MRA_E_NOREF: return "refset not loaded";
+    case MRA_E_NOMEM: return "out of device memory";
+    case MRA_E_DEVICE: return "device error";
+    case MRA_E_DEGENERATE: return "degenerate reference (zero norm)";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Shared constants, launch-argument structs and launcher declarations of
+// the MRA kernels (gfx950).  Host code includes this to launch; kernels
+// include it for the argument layouts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mra {
+
+constexpr int kNphi = 256;          // angles per ring (the paper's workloads)
+constexpr int kSlots = 128;         // frequency slots: f = 1..127, slot 0 = (f 0, f 128)
+constexpr int kRowTile = 8;         // particle rows (shift, particle) per correlation tile
+constexpr int kRefTile = 8;         // references per correlation tile
+constexpr int kPolarThreads = 512;  // 8 waves: one ring per wave, 8 shifts x 8 FFT lanes
+constexpr int kCorrThreads = 256;   // 4 waves
+constexpr int kAvgChunk = 64;       // particles per partial class sum
+constexpr int kAvgThreads = 256;
+
+enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+// Entry of the particle sampling stencil for ring r and angle j:
+// floor offsets (dx, dy) of r*(cos, sin)(theta_j) and the bilinear fractions.
+struct __attribute__((aligned(16))) Stencil {
+  int dx, dy;
+  float fx, fy;
+};
+
+// Resample + ring-FFT kernel.  out layout depends on the mode:
+//  mode 0: correlation operand A, [row tile][slot][t < R4][64] float, lane
+//          index g*16 + p*8 + row%8 (ring = g*R4 + t; p = 0: a-b, p = 1: a+b)
+//  mode 1: polar samples [n][S][R][256]
+//  mode 2: ring spectra  [n][S][R][129][2]
+struct PolarArgs {
+  const float* parts;  // first particle of the chunk, [n][L][L]
+  int n_part;
+  int L, R, R4, T, S1, S;
+  int Lp, pad, cx;     // LDS image side (with zero border), border width, centre
+  const Stencil* stencil;  // [R][256]
+  const float2* cs32;      // (cos, sin)(2 pi j / 256)
+  float* out;
+};
+
+// Fused contraction + inverse FFT over angle + arg-max.
+struct CorrArgs {
+  const float* A;        // [row tiles][128][R4][64]
+  int n_row_tiles;
+  int rows;              // valid rows in the chunk (n * S)
+  const float* B32;      // [ref tiles][128][R4][64]
+  const uint16_t* B16;   // [ref tiles][128][NS][64][8]
+  int R4, NS, n_ref_tiles, K, S, M;
+  const float* maxabs;   // FP16: device max |pixel| of the chunk (A scale), else null
+  float b_scale;         // FP16: power-of-two scale folded into B16
+  const float2* cs32;
+  float* row_cc;         // [rows] best CC of the row
+  int* row_idx;          // [rows] flat index of the row's best
+  float* table;          // debug: [n][K][M][S][256], else null
+};
+
+struct MergeArgs {
+  const float* row_cc;
+  const int* row_idx;
+  int n_part, S, S1, T, M;
+  int64_t out_off;
+  int32_t *ref, *shift_x, *shift_y, *psi, *mirror, *flat;
+  float *cc, *cc2;
+};
+
+struct RescoreArgs {
+  const float* parts;
+  int n_part;
+  int64_t out_off;
+  int L, R, r_min, Lp, pad, cx, K, T;
+  const Stencil* stencil;
+  const float* qhat;     // [K][R][256]
+  const int32_t *ref, *shift_x, *shift_y, *psi, *mirror;
+  float* cc;
+};
+
+// ---- launchers (one .hip file each) ----
+hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st);
+size_t polar_lds_bytes(int Lp);
+hipError_t launch_corr(int prec, bool table, const CorrArgs& a, hipStream_t st);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t st);
+hipError_t launch_rescore(const RescoreArgs& a, hipStream_t st);
+hipError_t launch_maxabs(const float* x, int64_t n, float* out, hipStream_t st);
+
+// reference preparation
+struct RefArgs {
+  const float* refs;
+  int K, L, r_min, R, R4, NS, n_ref_tiles, normalize, prec;
+  const double2* cs64;
+  double* q64;       // [K][R][256]
+  double* inv;       // [K]  1/norm (or 1)
+  double* norm;      // [K]
+  double2* Qs;       // [K][129][R]  w_r Q / (norm 256)
+  float* qhat32;     // [K][R][256]
+  float* B32;
+  uint16_t* B16;
+  float* bmax;       // device scalar: max |B| (for the FP16 scale)
+  float b_scale;
+};
+hipError_t launch_ref_stage1(const RefArgs& a, hipStream_t st);  // polar, norm, spectra, qhat, bmax
+hipError_t launch_ref_stage2(const RefArgs& a, hipStream_t st);  // pack B32 / B16
+
+// class averages
+struct AvgArgs {
+  const float* parts;
+  int64_t N;
+  int K, L, cx;
+  const int32_t *ref, *shift_x, *shift_y, *psi, *mirror;
+  const double2* cs64;
+  int n_blk;            // ceil(N / 1024)
+  int* blk_cnt;         // [n_blk][K]
+  int* blk_off;         // [n_blk][K]
+  int* cls_start;       // [K + 1]
+  int* chunk_start;     // [K + 1]
+  int* order;           // [N]
+  int max_chunks;
+  float* partial;       // [max_chunks][L*L]
+  float* averages;      // [K][L][L] in/out
+  int32_t* counts;      // [K]
+};
+hipError_t launch_averages(const AvgArgs& a, hipStream_t st);
+
+}  // namespace mra

@@ -1,0 +1,270 @@
+"""Thin ctypes binding over libmra.so (C ABI declared in include/mra.h).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+kernels of libmra.so.  PyTorch provides device memory and the stream; the
+library is bound to torch's HIP runtime by importing torch first.  If the
+library has not been built, every call fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmra.so")
+
+MRA_OK, MRA_E_INVAL, MRA_E_NOREF, MRA_E_NOMEM, MRA_E_DEVICE, MRA_E_DEGENERATE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+EXPORTS = (
+    "mra_create", "mra_destroy", "mra_load_refs", "mra_unload_refs", "mra_refset_info",
+    "mra_align", "mra_update_averages", "mra_align_batch", "mra_debug_polar",
+    "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_last_error",
+    "mra_strerror",
+)
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("L", "r_min", "r_max", "n_phi", "shift_max", "mirror", "precision", "normalize")]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ref", ctypes.c_void_p), ("shift_x", ctypes.c_void_p), ("shift_y", ctypes.c_void_p),
+                ("psi", ctypes.c_void_p), ("mirror", ctypes.c_void_p), ("cc", ctypes.c_void_p),
+                ("cc2", ctypes.c_void_p), ("flat_index", ctypes.c_void_p)]
+
+
+class Stack(ctypes.Structure):
+    _fields_ = [("refset_id", ctypes.c_int32), ("parts", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("shift_max", ctypes.c_int32), ("out", Result)]
+
+
+class MRAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libmra.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2011_05755_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "mra_create": [ctypes.POINTER(vp), ctypes.c_int, vp, u64],
+        "mra_destroy": [vp],
+        "mra_load_refs": [vp, i32, vp, i32, ctypes.POINTER(Geom)],
+        "mra_unload_refs": [vp, i32],
+        "mra_refset_info": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(Geom)],
+        "mra_align": [vp, i32, vp, i64, ctypes.POINTER(Result)],
+        "mra_update_averages": [vp, i32, vp, i64, ctypes.POINTER(Result), vp, vp],
+        "mra_align_batch": [vp, ctypes.POINTER(Stack), i32],
+        "mra_debug_polar": [vp, i32, vp, i64, vp],
+        "mra_debug_spectra": [vp, i32, vp, i64, vp],
+        "mra_debug_cctable": [vp, i32, vp, i64, vp],
+        "mra_debug_refs": [vp, i32, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.mra_last_error.argtypes = [vp]
+    lib.mra_last_error.restype = ctypes.c_char_p
+    lib.mra_strerror.argtypes = [ctypes.c_int]
+    lib.mra_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class AlignResult:
+    """Per-particle alignment parameters (device tensors of length N)."""
+
+    ref: torch.Tensor
+    shift_x: torch.Tensor
+    shift_y: torch.Tensor
+    psi: torch.Tensor
+    mirror: torch.Tensor
+    cc: torch.Tensor
+    cc2: torch.Tensor | None = None
+    flat_index: torch.Tensor | None = None
+
+    @classmethod
+    def empty(cls, N: int, device, with_cc2=False, with_flat=True):
+        i = dict(dtype=torch.int32, device=device)
+        return cls(ref=torch.empty(N, **i), shift_x=torch.empty(N, **i), shift_y=torch.empty(N, **i),
+                   psi=torch.empty(N, **i), mirror=torch.empty(N, **i),
+                   cc=torch.empty(N, dtype=torch.float32, device=device),
+                   cc2=torch.empty(N, dtype=torch.float32, device=device) if with_cc2 else None,
+                   flat_index=torch.empty(N, **i) if with_flat else None)
+
+    def c_struct(self) -> Result:
+        return Result(*(_ptr(getattr(self, f)) for f in
+                        ("ref", "shift_x", "shift_y", "psi", "mirror", "cc", "cc2", "flat_index")))
+
+    def narrow(self, lo: int, n: int) -> "AlignResult":
+        return AlignResult(**{f.name: (None if getattr(self, f.name) is None else getattr(self, f.name)[lo:lo + n])
+                              for f in dataclasses.fields(self)})
+
+    def to_numpy(self) -> dict:
+        return {f.name: getattr(self, f.name).cpu().numpy() for f in dataclasses.fields(self)
+                if getattr(self, f.name) is not None}
+
+
+@dataclasses.dataclass
+class Refset:
+    id: int
+    K: int
+    L: int
+    r_min: int
+    r_max: int
+    n_phi: int
+    shift_max: int
+    mirror: int
+    precision: str
+    normalize: int
+
+    @property
+    def n_rings(self):
+        return self.r_max - self.r_min + 1
+
+
+def _check_images(x: torch.Tensor, L: int, name: str):
+    if not (x.is_cuda and x.dtype == torch.float32 and x.dim() == 3 and x.shape[1] == L
+            and x.shape[2] == L and x.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor [N, {L}, {L}]")
+
+
+class Context:
+    """One libmra context bound to a device and a stream (default: torch's
+    current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None, workspace_cap: int = 0):
+        self.lib = load_library()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        rc = self.lib.mra_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.c_uint64(workspace_cap))
+        if rc != MRA_OK:
+            raise MRAError(rc, "mra_create failed: " + self.lib.mra_strerror(rc).decode())
+        self._h = h
+        self.refsets: dict[int, Refset] = {}
+
+    def _check(self, rc: int):
+        if rc != MRA_OK:
+            raise MRAError(rc, self.lib.mra_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.mra_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- reference sets ----
+    def load_refs(self, refset_id: int, refs: torch.Tensor, r_min: int, r_max: int, shift_max: int,
+                  n_phi: int = 256, mirror: bool = True, precision: str = "fp32", normalize: bool = True) -> Refset:
+        L = refs.shape[-1]
+        _check_images(refs, L, "refs")
+        g = Geom(L, r_min, r_max, n_phi, shift_max, int(mirror), PRECISIONS[precision], int(normalize))
+        self._check(self.lib.mra_load_refs(self._h, refset_id, _ptr(refs), refs.shape[0], ctypes.byref(g)))
+        rs = Refset(refset_id, refs.shape[0], L, r_min, r_max, n_phi, shift_max, int(mirror), precision,
+                    int(normalize))
+        self.refsets[refset_id] = rs
+        return rs
+
+    def unload_refs(self, refset_id: int):
+        self._check(self.lib.mra_unload_refs(self._h, refset_id))
+        self.refsets.pop(refset_id, None)
+
+    # ---- alignment ----
+    def align(self, refset_id: int, parts: torch.Tensor, out: AlignResult | None = None,
+              with_cc2: bool = False) -> AlignResult:
+        rs = self.refsets[refset_id]
+        _check_images(parts, rs.L, "parts")
+        N = parts.shape[0]
+        if out is None:
+            out = AlignResult.empty(N, parts.device, with_cc2=with_cc2)
+        res = out.c_struct()
+        self._check(self.lib.mra_align(self._h, refset_id, _ptr(parts), N, ctypes.byref(res)))
+        return out
+
+    def align_batch(self, stacks: list[tuple[int, torch.Tensor, int, AlignResult]]):
+        """stacks: list of (refset_id, parts, shift_max (-1: refset's), out)."""
+        arr = (Stack * len(stacks))()
+        for i, (rid, parts, T, out) in enumerate(stacks):
+            _check_images(parts, self.refsets[rid].L, "parts")
+            arr[i] = Stack(rid, parts.data_ptr(), parts.shape[0], T, out.c_struct())
+        self._check(self.lib.mra_align_batch(self._h, arr, len(stacks)))
+
+    def update_averages(self, refset_id: int, parts: torch.Tensor, params: AlignResult,
+                        averages: torch.Tensor) -> torch.Tensor:
+        """In place: averages [K, L, L] (previous Y in, Y' out).  Returns counts [K]."""
+        rs = self.refsets[refset_id]
+        _check_images(parts, rs.L, "parts")
+        _check_images(averages, rs.L, "averages")
+        if averages.shape[0] != rs.K:
+            raise ValueError("averages must have K images")
+        counts = torch.empty(rs.K, dtype=torch.int32, device=parts.device)
+        p = params.c_struct()
+        self._check(self.lib.mra_update_averages(self._h, refset_id, _ptr(parts), parts.shape[0],
+                                                 ctypes.byref(p), _ptr(averages), _ptr(counts)))
+        return counts
+
+    # ---- debug exports ----
+    def debug_polar(self, refset_id: int, parts: torch.Tensor) -> torch.Tensor:
+        rs = self.refsets[refset_id]
+        S = (2 * rs.shift_max + 1) ** 2
+        out = torch.empty((parts.shape[0], S, rs.n_rings, rs.n_phi), dtype=torch.float32, device=parts.device)
+        self._check(self.lib.mra_debug_polar(self._h, refset_id, _ptr(parts), parts.shape[0], _ptr(out)))
+        return out
+
+    def debug_spectra(self, refset_id: int, parts: torch.Tensor) -> torch.Tensor:
+        rs = self.refsets[refset_id]
+        S = (2 * rs.shift_max + 1) ** 2
+        out = torch.empty((parts.shape[0], S, rs.n_rings, rs.n_phi // 2 + 1, 2), dtype=torch.float32,
+                          device=parts.device)
+        self._check(self.lib.mra_debug_spectra(self._h, refset_id, _ptr(parts), parts.shape[0], _ptr(out)))
+        return out
+
+    def debug_cctable(self, refset_id: int, parts: torch.Tensor) -> torch.Tensor:
+        rs = self.refsets[refset_id]
+        S1 = 2 * rs.shift_max + 1
+        M = 2 if rs.mirror else 1
+        out = torch.empty((parts.shape[0], rs.K, M, S1, S1, rs.n_phi), dtype=torch.float32, device=parts.device)
+        self._check(self.lib.mra_debug_cctable(self._h, refset_id, _ptr(parts), parts.shape[0], _ptr(out)))
+        return out
+
+    def debug_refs(self, refset_id: int):
+        rs = self.refsets[refset_id]
+        dev = torch.device("cuda", self.device)
+        qhat = torch.empty((rs.K, rs.n_rings, rs.n_phi), dtype=torch.float32, device=dev)
+        norm = torch.empty(rs.K, dtype=torch.float64, device=dev)
+        self._check(self.lib.mra_debug_refs(self._h, refset_id, _ptr(qhat), _ptr(norm)))
+        return qhat, norm
