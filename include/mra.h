@@ -165,6 +165,14 @@ int mra_debug_spectra(mra_ctx* ctx, int32_t refset_id, const float* parts, int64
 int mra_debug_cctable(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N, float* out);
 int mra_debug_refs(mra_ctx* ctx, int32_t refset_id, float* qhat, double* norm);
 
+/* Kernel timing for measurement.  mra_profile(ctx, 1) clears and starts
+ * recording a HIP event pair around every launch of the named kernel groups
+ * ("polar", "corr", "merge", "rescore", "averages") on the context's stream;
+ * mra_profile(ctx, 0) stops.  mra_profile_read synchronises the stream and
+ * returns the summed device time and the launch count of one group. */
+int mra_profile(mra_ctx* ctx, int enable);
+int mra_profile_read(mra_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+
 const char* mra_last_error(mra_ctx* ctx);
 const char* mra_strerror(int code);
 

@@ -53,6 +53,8 @@ struct mra_ctx {
   double2* cs64 = nullptr;
   float2* cs32 = nullptr;
   std::map<std::string, DevBuf> ws;
+  bool profiling = false;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
 };
 
 namespace {
@@ -85,6 +87,31 @@ void* ws_get(mra_ctx* c, const std::string& name, size_t bytes) {
     b.bytes = bytes;
   }
   return b.p;
+}
+
+// Runs `launch` between two events on the context stream when profiling.
+template <class F>
+void timed(mra_ctx* c, const char* group, F&& launch) {
+  if (!c->profiling) {
+    launch();
+    return;
+  }
+  hipEvent_t a, b;
+  hip_check(c, hipEventCreate(&a), "hipEventCreate");
+  hip_check(c, hipEventCreate(&b), "hipEventCreate");
+  hip_check(c, hipEventRecord(a, c->stream), "hipEventRecord");
+  launch();
+  hip_check(c, hipEventRecord(b, c->stream), "hipEventRecord");
+  c->prof[group].emplace_back(a, b);
+}
+
+void clear_profile(mra_ctx* c) {
+  for (auto& kv : c->prof)
+    for (auto& e : kv.second) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  c->prof.clear();
 }
 
 void free_refset(Refset& r) {
@@ -192,7 +219,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   if (rs.g.precision == kFP16) {
     maxabs = (float*)ws_get(c, "maxabs", 256);
     hip_check(c, hipMemsetAsync(maxabs, 0, sizeof(float), st), "memset");
-    hip_check(c, launch_maxabs(src, (int64_t)nc * L * L, maxabs, st), "maxabs");
+    timed(c, "maxabs", [&] { hip_check(c, launch_maxabs(src, (int64_t)nc * L * L, maxabs, st), "maxabs"); });
   }
 
   PolarArgs pa{};
@@ -203,7 +230,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   pa.stencil = rs.stencil;
   pa.cs32 = c->cs32;
   pa.out = A;
-  hip_check(c, launch_polar(0, pa, st), "polar");
+  timed(c, "polar", [&] { hip_check(c, launch_polar(0, pa, st), "polar"); });
 
   CorrArgs ca{};
   ca.A = A;
@@ -218,7 +245,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.row_cc = rcc;
   ca.row_idx = ridx;
   ca.table = table;
-  hip_check(c, launch_corr(rs.g.precision, table != nullptr, ca, st), "corr");
+  timed(c, "corr", [&] { hip_check(c, launch_corr(rs.g.precision, table != nullptr, ca, st), "corr"); });
   if (table) return;
 
   MergeArgs ma{};
@@ -228,7 +255,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ma.ref = out->ref; ma.shift_x = out->shift_x; ma.shift_y = out->shift_y;
   ma.psi = out->psi; ma.mirror = out->mirror; ma.flat = out->flat_index;
   ma.cc = out->cc; ma.cc2 = out->cc2;
-  hip_check(c, launch_merge(ma, st), "merge");
+  timed(c, "merge", [&] { hip_check(c, launch_merge(ma, st), "merge"); });
 
   if (rs.g.precision != kFP32) {
     RescoreArgs ra{};
@@ -242,7 +269,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
     ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
     ra.psi = out->psi; ra.mirror = out->mirror;
     ra.cc = out->cc;
-    hip_check(c, launch_rescore(ra, st), "rescore");
+    timed(c, "rescore", [&] { hip_check(c, launch_rescore(ra, st), "rescore"); });
   }
 }
 
@@ -328,6 +355,7 @@ int mra_destroy(mra_ctx* c) {
   if (!c) return MRA_E_INVAL;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  clear_profile(c);
   for (auto& kv : c->refs) free_refset(kv.second);
   for (auto& kv : c->ws)
     if (kv.second.p) (void)hipFree(kv.second.p);
@@ -493,7 +521,7 @@ int mra_update_averages(mra_ctx* c, int32_t id, const float* parts, int64_t N, c
     a.partial = (float*)ws_get(c, "avg_partial", (size_t)a.max_chunks * L * L * sizeof(float));
     a.averages = averages;
     a.counts = counts;
-    hip_check(c, launch_averages(a, st), "averages");
+    timed(c, "averages", [&] { hip_check(c, launch_averages(a, st), "averages"); });
   });
 }
 
@@ -537,6 +565,33 @@ int mra_debug_refs(mra_ctx* c, int32_t id, float* qhat, double* norm) {
       hip_check(c, hipMemcpyAsync(qhat, rs.qhat, (size_t)rs.K * rs.R * kNphi * sizeof(float), hipMemcpyDeviceToDevice, c->stream), "memcpy");
     if (norm)
       hip_check(c, hipMemcpyAsync(norm, rs.norm, (size_t)rs.K * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "memcpy");
+  });
+}
+
+int mra_profile(mra_ctx* c, int enable) {
+  return guard(c, [&] {
+    hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (enable) clear_profile(c);
+    c->profiling = enable != 0;
+  });
+}
+
+int mra_profile_read(mra_ctx* c, const char* kernel, double* total_ms, int64_t* launches) {
+  return guard(c, [&] {
+    if (!kernel) throw Fail{MRA_E_INVAL, "kernel name is NULL"};
+    hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    double tot = 0.0;
+    int64_t cnt = 0;
+    auto it = c->prof.find(kernel);
+    if (it != c->prof.end())
+      for (auto& e : it->second) {
+        float ms = 0.f;
+        hip_check(c, hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+        tot += ms;
+        ++cnt;
+      }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
   });
 }
 

@@ -22,8 +22,8 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 EXPORTS = (
     "mra_create", "mra_destroy", "mra_load_refs", "mra_unload_refs", "mra_refset_info",
     "mra_align", "mra_update_averages", "mra_align_batch", "mra_debug_polar",
-    "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_last_error",
-    "mra_strerror",
+    "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_profile", "mra_profile_read",
+    "mra_last_error", "mra_strerror",
 )
 
 
@@ -74,6 +74,8 @@ def load_library() -> ctypes.CDLL:
         "mra_debug_spectra": [vp, i32, vp, i64, vp],
         "mra_debug_cctable": [vp, i32, vp, i64, vp],
         "mra_debug_refs": [vp, i32, vp, vp],
+        "mra_profile": [vp, ctypes.c_int],
+        "mra_profile_read": [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +238,17 @@ class Context:
         self._check(self.lib.mra_update_averages(self._h, refset_id, _ptr(parts), parts.shape[0],
                                                  ctypes.byref(p), _ptr(averages), _ptr(counts)))
         return counts
+
+    # ---- kernel timing ----
+    def profile(self, enable: bool):
+        self._check(self.lib.mra_profile(self._h, int(enable)))
+
+    def profile_read(self, kernel: str) -> tuple[float, int]:
+        """(summed device milliseconds, launches) of a kernel group since profile(True)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.mra_profile_read(self._h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     # ---- debug exports ----
     def debug_polar(self, refset_id: int, parts: torch.Tensor) -> torch.Tensor:
