@@ -13,7 +13,7 @@ constexpr int kSlots = 128;         // frequency slots: f = 1..127, slot 0 = (f 
 constexpr int kRowTile = 8;         // particle rows (shift, particle) per correlation tile
 constexpr int kRefTile = 8;         // references per correlation tile
 constexpr int kPolarThreads = 512;  // 8 waves: one ring per wave, 8 shifts x 8 FFT lanes
-constexpr int kCorrThreads = 256;   // 4 waves
+constexpr int kCorrThreads = 512;   // 8 waves
 constexpr int kAvgChunk = 64;       // particles per partial class sum
 constexpr int kAvgThreads = 256;
 
