@@ -83,6 +83,16 @@ struct Op16<kFP16> {
   }
 };
 
+// Particle operand of lane ln for slot `slot`: ring g*R4 + t of lane group
+// g = ln/16 at element t*16 (A layout [tile][slot][ring][16]).  Rings >= R
+// are padding that the polar kernel never writes: callers mask them.
+__device__ __forceinline__ const float* a_lane(const CorrArgs& a, int R4, int tile, int slot, int ln) {
+  return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
+}
+__device__ __forceinline__ bool ring_ok(const CorrArgs& a, int R4, int ln, int t) {
+  return (ln >> 4) * R4 + t < a.R;
+}
+
 // store a 16x16 MFMA block of slot `slot` into the LDS spectrum state
 __device__ __forceinline__ void store_block(float* st, int slot, int ln, f32x4 acc) {
   const int p = ln >> 5, q = (ln >> 3) & 1, ref = ln & 7, row0 = ((ln >> 4) & 1) * 4;
@@ -106,9 +116,9 @@ struct Fp32Contract {
     if (kResident) {
 #pragma unroll
       for (int i = 0; i < kSlotsPerWave; ++i) {
-        const float* ap = a.A + ((size_t)(tile * kSlots + w + kCorrWaves * i) * RT) * 64 + ln;
+        const float* ap = a_lane(a, RT, tile, w + kCorrWaves * i, ln);
 #pragma unroll
-        for (int t = 0; t < RT; ++t) areg[i][t] = __builtin_nontemporal_load(ap + t * 64);
+        for (int t = 0; t < RT; ++t) areg[i][t] = ring_ok(a, RT, ln, t) ? __builtin_nontemporal_load(ap + t * 16) : 0.f;
       }
     }
   }
@@ -125,9 +135,9 @@ struct Fp32Contract {
       float av[4][kResident ? 1 : RT];
       auto loada = [&](int i, float (&dst)[kResident ? 1 : RT]) {
         if constexpr (!kResident) {
-          const float* ap = a.A + ((size_t)(tile * kSlots + w + kCorrWaves * i) * RT) * 64 + ln;
+          const float* ap = a_lane(a, RT, tile, w + kCorrWaves * i, ln);
 #pragma unroll
-          for (int t = 0; t < RT; ++t) dst[t] = ap[t * 64];
+          for (int t = 0; t < RT; ++t) dst[t] = ring_ok(a, RT, ln, t) ? ap[t * 16] : 0.f;
         }
       };
       loadb(0, b[0]);
@@ -159,11 +169,11 @@ struct Fp32Contract {
     } else {
       for (int i = 0; i < kSlotsPerWave; ++i) {
         const int slot = w + kCorrWaves * i;
-        const float* ap = a.A + ((size_t)(tile * kSlots + slot) * R4) * 64 + ln;
+        const float* ap = a_lane(a, R4, tile, slot, ln);
         const float* bp = a.B32 + ((size_t)(kt * kSlots + slot) * R4) * 64 + ln;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         for (int t = 0; t < R4; ++t)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[t * 64], bp[t * 64], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ring_ok(a, R4, ln, t) ? ap[t * 16] : 0.f, bp[t * 64], acc, 0, 0, 0);
         store_block(st, slot, ln, acc);
       }
     }
@@ -187,27 +197,39 @@ struct Half16Contract {
   }
 
   __device__ __forceinline__ V conv(const CorrArgs& a, int tile, int slot, int s, int ln, float scale) {
-    const float* ap = a.A + ((size_t)(tile * kSlots + slot) * a.R4) * 64 + ln;
+    const float* ap = a_lane(a, a.R4, tile, slot, ln);
     float v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int t = 8 * s + e;
-      v[e] = t < a.R4 ? ap[t * 64] * scale : 0.f;
+      v[e] = (t < a.R4 && ring_ok(a, a.R4, ln, t)) ? ap[t * 16] * scale : 0.f;
     }
     return Op16<PREC>::cvt(v);
   }
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln, float scale) {
     if constexpr (RT > 0) {
+      // issue the loads of 4 slots before converting any of them, so the
+      // memory latency is paid 4 times per workgroup instead of 16
+      constexpr int kBatch = RT <= 9 ? 4 : 2;
 #pragma unroll
-      for (int i = 0; i < kSlotsPerWave; ++i) {
-        const float* ap = a.A + ((size_t)(tile * kSlots + w + kCorrWaves * i) * RT) * 64 + ln;
-        float v[8 * kNS];
+      for (int i0 = 0; i0 < kSlotsPerWave; i0 += kBatch) {
+        float v[kBatch][RT];
 #pragma unroll
-        for (int t = 0; t < 8 * kNS; ++t) v[t] = t < RT ? __builtin_nontemporal_load(ap + t * 64) * scale : 0.f;
+        for (int b = 0; b < kBatch; ++b) {
+          const float* ap = a_lane(a, RT, tile, w + kCorrWaves * (i0 + b), ln);
 #pragma unroll
-        for (int d = 0; d < 4 * kNS; ++d)
-          areg[i][d / 4][d % 4] = d < kW ? ((uint32_t)bits(v[2 * d]) | ((uint32_t)bits(v[2 * d + 1]) << 16)) : 0u;
+          for (int t = 0; t < RT; ++t) v[b][t] = __builtin_nontemporal_load(ap + t * 16);
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+          for (int d = 0; d < 4 * kNS; ++d) {
+            const int t0 = 2 * d, t1 = 2 * d + 1;
+            const float x0 = (t0 < RT && ring_ok(a, RT, ln, t0)) ? v[b][t0 < RT ? t0 : 0] * scale : 0.f;
+            const float x1 = (t1 < RT && ring_ok(a, RT, ln, t1)) ? v[b][t1 < RT ? t1 : 0] * scale : 0.f;
+            areg[i0 + b][d / 4][d % 4] = d < kW ? ((uint32_t)bits(x0) | ((uint32_t)bits(x1) << 16)) : 0u;
+          }
       }
     }
   }

@@ -44,8 +44,14 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
   extern __shared__ float smem[];
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
-  const int n = blockIdx.x;
+  float2* tw = scr + 8 * 64 * 17;  // exp(-2 pi i e / 256), e = 0..255
+  // consecutive particles on the same XCD (workgroups are dealt to the 8
+  // XCDs round-robin), so row tiles shared by neighbours meet in one L2
+  const int per_xcd = gridDim.x / 8;
+  const int n = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (n >= a.n_part) return;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
+  if (threadIdx.x < kNphi) tw[threadIdx.x] = w256f(a.cs32, threadIdx.x);
   __syncthreads();
 
   const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
       for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
       dft16<-1>(z);
 #pragma unroll
-      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], w256f(a.cs32, 2 * ((l * k1) & 127)));
+      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((l * k1) & 127)]);
 #pragma unroll
       for (int k1 = 0; k1 < 16; ++k1) my[(rl * 8 + l) * 17 + k1] = z[k1];
       wave_sync();
@@ -105,10 +111,9 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
 
       if (MODE == 0) {
         const int row = n * a.S + s;
-        const int g = ring / a.R4, t = ring - g * a.R4;
-        float* o = a.out + (size_t)(row >> 3) * kSlots * a.R4 * 64 + t * 64 + g * 16 + (row & 7);
+        float* o = a.out + (size_t)(row >> 3) * kSlots * a.R4 * 64 + ring * 16 + (row & 7);
         const size_t slot_stride = (size_t)a.R4 * 64;
-        fwd_emit(l, Za, Zb, [&](int f) { return w256f(a.cs32, f); },
+        fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
                    if (!valid) return;
                    o[slot * slot_stride] = re - im;
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
                  });
       } else {  // MODE 2: plain spectra
         float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * 129 * 2;
-        fwd_emit(l, Za, Zb, [&](int f) { return w256f(a.cs32, f); },
+        fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
                    if (!valid) return;
                    if (slot == 0) {
@@ -133,13 +138,13 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
 }
 
 size_t polar_lds_bytes(int Lp) {
-  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)8 * 64 * 17 * sizeof(float2);
+  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)(8 * 64 * 17 + kNphi) * sizeof(float2);
 }
 
 hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
   if (a.n_part <= 0) return hipSuccess;
   const size_t lds = polar_lds_bytes(a.Lp);
-  dim3 grid(a.n_part), block(kPolarThreads);
+  dim3 grid((a.n_part + 7) / 8 * 8), block(kPolarThreads);
   switch (mode) {
     case 0: hipLaunchKernelGGL(k_polar_fft<0>, grid, block, lds, st, a); break;
     case 1: hipLaunchKernelGGL(k_polar_fft<1>, grid, block, lds, st, a); break;

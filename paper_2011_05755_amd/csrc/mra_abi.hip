@@ -238,7 +238,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.rows = rows;
   ca.B32 = rs.B32;
   ca.B16 = rs.B16;
-  ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = p.S; ca.M = p.M;
+  ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = p.S; ca.M = p.M;
   ca.maxabs = maxabs;
   ca.b_scale = rs.b_scale;
   ca.cs32 = c->cs32;

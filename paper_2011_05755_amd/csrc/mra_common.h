@@ -27,8 +27,9 @@ struct __attribute__((aligned(16))) Stencil {
 };
 
 // Resample + ring-FFT kernel.  out layout depends on the mode:
-//  mode 0: correlation operand A, [row tile][slot][t < R4][64] float, lane
-//          index g*16 + p*8 + row%8 (ring = g*R4 + t; p = 0: a-b, p = 1: a+b)
+//  mode 0: correlation operand A, [row tile][slot][ring < 4*R4][16] float,
+//          inner index p*8 + row%8 (p = 0: a-b, p = 1: a+b); rings >= R are
+//          never written (the correlation kernel masks them)
 //  mode 1: polar samples [n][S][R][256]
 //  mode 2: ring spectra  [n][S][R][129][2]
 struct PolarArgs {
@@ -43,12 +44,12 @@ struct PolarArgs {
 
 // Fused contraction + inverse FFT over angle + arg-max.
 struct CorrArgs {
-  const float* A;        // [row tiles][128][R4][64]
+  const float* A;        // [row tiles][128][4*R4][16]
   int n_row_tiles;
   int rows;              // valid rows in the chunk (n * S)
   const float* B32;      // [ref tiles][128][R4][64]
   const uint16_t* B16;   // [ref tiles][128][NS][64][8]
-  int R4, NS, n_ref_tiles, K, S, M;
+  int R, R4, NS, n_ref_tiles, K, S, M;
   const float* maxabs;   // FP16: device max |pixel| of the chunk (A scale), else null
   float b_scale;         // FP16: power-of-two scale folded into B16
   const float2* cs32;
