@@ -57,10 +57,15 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
   const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int l = ln >> 3, rl = ln & 7;
   float2* my = scr + w * 64 * 17;
+  float* stage = reinterpret_cast<float*>(my);  // [128 slots][16] after the transpose
   int k1a, k1b;
   fwd_cols(l, k1a, k1b);
   const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
-  const int ngrp = (a.S + 7) >> 3;
+  // lane rl handles row (q0 + grp) * 8 + rl: groups are aligned to the
+  // correlation kernel's 8-row tiles
+  const int row0 = n * a.S;
+  const int q0 = row0 >> 3;
+  const int ngrp = ((row0 + a.S - 1) >> 3) - q0 + 1;
 
   for (int ring = w; ring < a.R; ring += 8) {
     int off[32];
@@ -73,9 +78,10 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
       fy[i] = s.fy;
     }
     for (int grp = 0; grp < ngrp; ++grp) {
-      const int s = grp * 8 + rl;
-      const bool valid = s < a.S;
-      const int sc = valid ? s : a.S - 1;
+      const int row = (q0 + grp) * 8 + rl;
+      const int s = row - row0;
+      const bool valid = s >= 0 && s < a.S;
+      const int sc = s < 0 ? 0 : (s < a.S ? s : a.S - 1);
       const int soff = (sc / a.S1 - a.T) * a.Lp + (sc % a.S1 - a.T);
       float v[32];
 #pragma unroll
@@ -110,17 +116,39 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
       dft8<-1>(Zb);
 
       if (MODE == 0) {
-        const int row = n * a.S + s;
-        float* o = a.out + (size_t)(row >> 3) * kSlots * a.R4 * 64 + ring * 16 + (row & 7);
-        const size_t slot_stride = (size_t)a.R4 * 64;
+        // stage [slot][p*8 + row] in this wave's scratch, then write whole
+        // 64-byte (slot, ring) segments of the tile with 16-byte stores
         fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
-                   if (!valid) return;
-                   o[slot * slot_stride] = re - im;
-                   o[slot * slot_stride + 8] = re + im;
+                   stage[slot * 16 + rl] = re - im;
+                   stage[slot * 16 + 8 + rl] = re + im;
                  });
+        wave_sync();
+        const int tile = q0 + grp;
+        const int first = row0 - tile * 8;            // rows of this tile before the particle
+        const int last = row0 + a.S - tile * 8;       // first row after the particle
+        float* dst = a.out + (size_t)tile * kSlots * a.R4 * 64 + ring * 16;
+        const size_t slot_stride = (size_t)a.R4 * 64;
+        const int part = ln & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
+        const int r0 = (part & 1) * 4;
+        const bool full = r0 >= first && r0 + 4 <= last;
+#pragma unroll
+        for (int it = 0; it < kSlots / 16; ++it) {
+          const int slot = it * 16 + (ln >> 2);
+          const float4 val = *reinterpret_cast<const float4*>(stage + slot * 16 + part * 4);
+          float* o = dst + slot * slot_stride + part * 4;
+          if (full) {
+            *reinterpret_cast<float4*>(o) = val;
+          } else {
+            if (r0 + 0 >= first && r0 + 0 < last) o[0] = val.x;
+            if (r0 + 1 >= first && r0 + 1 < last) o[1] = val.y;
+            if (r0 + 2 >= first && r0 + 2 < last) o[2] = val.z;
+            if (r0 + 3 >= first && r0 + 3 < last) o[3] = val.w;
+          }
+        }
+        wave_sync();
       } else {  // MODE 2: plain spectra
-        float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * 129 * 2;
+        float* o = a.out + (((size_t)n * a.S + (valid ? s : 0)) * a.R + ring) * 129 * 2;
         fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
                    if (!valid) return;
