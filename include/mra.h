@@ -148,10 +148,32 @@ int mra_update_averages(mra_ctx* ctx, int32_t refset_id, const float* parts, int
                         const mra_result* params, float* averages, int32_t* counts);
 
 /* Alignment of several stacks of uneven size (each against its own refset,
- * with its own shift range) in one call.  Each stack's results equal those
- * of mra_align on it alone.  Errors as mra_align, checked for every stack
- * before anything is enqueued. */
+ * with its own shift range) in one call.  Stacks are cut into pieces that
+ * fill the workspace; pieces with the same precision and tile variant share
+ * one persistent correlation launch (workgroups pull (stack, row tile) work
+ * items until all are done) and one launch of each per-particle kernel.
+ * Each stack's results equal those of mra_align on it alone.  Errors as
+ * mra_align, checked for every stack before anything is enqueued. */
 int mra_align_batch(mra_ctx* ctx, const mra_stack* stacks, int32_t n);
+
+/* Tile configuration of a refset's correlation kernel (chosen by the
+ * autotuner in paper_2011_05755_amd/autotune.py, or left at the default).
+ *  corr_variant  -1: default for the geometry.  FP32: 0 = 8 waves with the
+ *                particle operand held in registers (R4 = ceil(n_rings/4) <= 9),
+ *                1 = 4 waves, operand in registers (R4 <= 12), 2 = 8 waves,
+ *                operand streamed (any R4).  BF16/FP16: 0 = operand converted
+ *                once per row tile and held in registers, 1 = operand re-read
+ *                and converted per reference tile.  MRA_E_INVAL if the variant
+ *                cannot serve the geometry.
+ *  chunk_particles  particles per chunk (0: derived from the workspace cap);
+ *                also caps the pieces mra_align_batch cuts the refset's stacks into.
+ * Results do not depend on the tuning (bit for bit). */
+typedef struct mra_tuning {
+  int32_t corr_variant;
+  int32_t chunk_particles;
+} mra_tuning;
+int mra_set_tuning(mra_ctx* ctx, int32_t refset_id, const mra_tuning* t);
+int mra_get_tuning(mra_ctx* ctx, int32_t refset_id, mra_tuning* t);
 
 /* Debug exports (same kernels as the production path).
  *  mra_debug_polar:    float32 [N][S][n_rings][n_phi] unmirrored polar

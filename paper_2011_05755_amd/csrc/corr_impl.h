@@ -1,0 +1,486 @@
+// Ring-weighted correlation of every particle row with every reference
+// (Sec. 3: FFT(x)' x FFT(y) per ring, references on a second grid axis,
+// inverse FFT of the CC table, arg-max by reduction as in Fig. 2), fused so
+// that the CC table is never written to memory.
+//
+// A workgroup owns 8 particle rows (row = particle * S + shift) and loops
+// over all references in tiles of 8.  For each frequency slot f the matrix
+// cores compute the 16 x 16 block
+//     U[(p,row), (q,ref)] = sum_r A_f[(p,row), r] * B_f[r, (q,ref)],
+//     A rows: p = 0 -> a - b, p = 1 -> a + b  (particle spectrum a + ib)
+//     B cols: q = 0 -> c - d, q = 1 -> c + d  (reference spectrum c + id,
+//             weighted by w_r, divided by the ring norm and by 256)
+// whose four entries per (row, ref) are the spectrum H of the complex signal
+// c0 + i c1 (unmirrored CC + i * mirrored CC) at f and 256 - f (see
+// mra_fft.h).  The 128 slots of all 64 (row, ref) pairs sit in LDS (128 KiB);
+// then a 16 x 16 inverse FFT over angle (two passes through LDS) yields the
+// CC at all 256 angles for both mirrors, and the running maximum with the
+// smallest-flat-index tie rule is kept per row across reference tiles.
+//
+// NW waves (8, or 4 in one FP32 variant): wave w owns slots w, w+NW, ... in
+// the contraction.  In the resident variants the particle operand A of
+// those slots is read from HBM once per row tile and kept in registers (FP32:
+// R4 <= 9 with 8 waves, R4 <= 12 with 4 waves; packed 16-bit for the BF16 /
+// FP16 forms) for all reference tiles; the streamed variants re-read it per
+// reference tile.  The reference operand B is streamed from L2 with a slot
+// prefetch.  Variants are tile configurations that an autotuner chooses
+// between; they do not change any result.
+#pragma once
+#include <type_traits>
+
+#include "mra_common.h"
+#include "mra_fft.h"
+
+namespace mra {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxBatch = kMaxBatchPieces;
+
+__device__ __forceinline__ float2 w256c(const float2* cs, int e) {
+  float2 c = cs[e & 255];
+  return make_float2(c.x, -c.y);
+}
+
+// logical index j (0..255) of a pair's spectrum -> float2 index in LDS state
+__device__ __forceinline__ int vidx(int j, int P) {
+  const int slot = j < 128 ? j : ((256 - j) & 127);
+  const int half = j < 128 ? 0 : 1;
+  return (slot * 2 + half) * 64 + P;
+}
+
+__device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+template <int PREC>
+struct Op16;
+template <>
+struct Op16<kBF16> {
+  typedef bf16x8 T;
+  static __device__ __forceinline__ uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+  static __device__ __forceinline__ f32x4 mfma(T a, T b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Op16<kFP16> {
+  typedef f16x8 T;
+  static __device__ __forceinline__ uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+  static __device__ __forceinline__ f32x4 mfma(T a, T b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Particle operand of lane ln for slot `slot`: ring g*R4 + t of lane group
+// g = ln/16 at element t*16 (A layout [tile][slot][ring][16]).  Rings >= R
+// are padding that the polar kernel never writes: callers mask them.
+// RX > 0: R4 == RX is known at compile time.
+template <int RX = 0>
+__device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int slot, int ln) {
+  const int R4 = RX > 0 ? RX : a.R4;
+  return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
+}
+template <int RX = 0>
+__device__ __forceinline__ bool ring_ok(const CorrArgs& a, int ln, int t) {
+  const int R4 = RX > 0 ? RX : a.R4;
+  return t < R4 && (ln >> 4) * R4 + t < a.R;
+}
+
+// store a 16x16 MFMA block of slot `slot` into the LDS spectrum state
+__device__ __forceinline__ void store_block(float* st, int slot, int ln, f32x4 acc) {
+  const int p = ln >> 5, q = (ln >> 3) & 1, ref = ln & 7, row0 = ((ln >> 4) & 1) * 4;
+#pragma unroll
+  for (int i2 = 0; i2 < 4; ++i2) {
+    const int P = (row0 + i2) * 8 + ref;
+    st[((slot * 2 + p) * 64 + P) * 2 + (q ^ p)] = acc[i2];
+  }
+}
+
+// Contraction of one reference tile with FP32 operands for the wave's
+// 128/NW slots (slot = w + NW*i).  EXACT: R4 == MAXR, else R4 <= MAXR at
+// run time (mixed ring counts in one batched launch).  RES: the
+// particle operand of all the wave's slots is loaded once per row tile and
+// kept in registers for every reference tile; otherwise it is streamed with
+// the reference operand.  Operands of the next two slots are prefetched.
+template <int NW, int MAXR, bool RES, bool EXACT>
+struct Fp32Contract {
+  static constexpr int SPW = kSlots / NW;
+  static constexpr int RX = EXACT ? MAXR : 0;
+  float areg[RES ? SPW : 1][RES ? MAXR : 1];
+
+  __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
+    if constexpr (RES) {
+#pragma unroll
+      for (int i = 0; i < SPW; ++i) {
+        const float* ap = a_lane<RX>(a, tile, w + NW * i, ln);
+#pragma unroll
+        for (int t = 0; t < MAXR; ++t) areg[i][t] = ring_ok<RX>(a, ln, t) ? __builtin_nontemporal_load(ap + t * 16) : 0.f;
+      }
+    }
+  }
+
+  __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
+    float b[4][MAXR];
+    float av[4][RES ? 1 : MAXR];
+    auto loadb = [&](int i, float (&dst)[MAXR]) {
+      const float* bp = a.B32 + ((size_t)(kt * kSlots + w + NW * i) * (EXACT ? MAXR : a.R4)) * 64 + ln;
+#pragma unroll
+      for (int t = 0; t < MAXR; ++t)
+        if (EXACT || t < a.R4) dst[t] = bp[t * 64];
+    };
+    auto loada = [&](int i, float (&dst)[RES ? 1 : MAXR]) {
+      if constexpr (!RES) {
+        const float* ap = a_lane<RX>(a, tile, w + NW * i, ln);
+#pragma unroll
+        for (int t = 0; t < MAXR; ++t) dst[t] = ring_ok<RX>(a, ln, t) ? ap[t * 16] : 0.f;
+      }
+    };
+    loadb(0, b[0]);
+    loada(0, av[0]);
+    loadb(1, b[1]);
+    loada(1, av[1]);
+#pragma unroll
+    for (int i = 0; i < SPW; i += 2) {
+      // two independent accumulation chains keep the matrix pipe busy
+      f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < MAXR; ++t) {
+        if (EXACT || t < a.R4) {
+          const float x0 = RES ? areg[i][RES ? t : 0] : av[i % 4][RES ? 0 : t];
+          const float x1 = RES ? areg[i + 1][RES ? t : 0] : av[(i + 1) % 4][RES ? 0 : t];
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, b[i % 4][t], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, b[(i + 1) % 4][t], acc1, 0, 0, 0);
+        }
+      }
+      if (i + 2 < SPW) {
+        loadb(i + 2, b[(i + 2) % 4]);
+        loada(i + 2, av[(i + 2) % 4]);
+      }
+      if (i + 3 < SPW) {
+        loadb(i + 3, b[(i + 3) % 4]);
+        loada(i + 3, av[(i + 3) % 4]);
+      }
+      store_block(st, w + NW * i, ln, acc0);
+      store_block(st, w + NW * (i + 1), ln, acc1);
+    }
+  }
+};
+
+// Contraction with 16-bit operands; NS = ceil(MAXR / 8) steps of 8 rings
+// per lane group, R4 <= MAXR (EXACT: every work item has ceil(R4 / 8) == NS).
+// RES: the particle operand is converted once per row tile (scaled for
+// FP16) and kept packed in registers, two values per dword; otherwise it is
+// re-read and converted per reference tile, one slot ahead.
+template <int PREC, int NW, int MAXR, bool EXACT, bool RES>
+struct Half16Contract {
+  static constexpr int SPW = kSlots / NW;
+  static constexpr int NS = (MAXR + 7) / 8;
+  typedef typename Op16<PREC>::T V;
+  u32x4 areg[RES ? SPW : 1][NS];
+  float scale_ = 1.f;
+
+  __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, float (&v)[8 * NS], bool nt) {
+    const float* ap = a_lane(a, tile, slot, ln);
+#pragma unroll
+    for (int t = 0; t < 8 * NS; ++t)
+      v[t] = (t < MAXR && ring_ok(a, ln, t)) ? (nt ? __builtin_nontemporal_load(ap + t * 16) : ap[t * 16]) : 0.f;
+  }
+  __device__ __forceinline__ void pack(const float (&v)[8 * NS], u32x4 (&dst)[NS]) const {
+#pragma unroll
+    for (int d = 0; d < 4 * NS; ++d)
+      dst[d / 4][d % 4] = (uint32_t)Op16<PREC>::bits(v[2 * d] * scale_) |
+                          ((uint32_t)Op16<PREC>::bits(v[2 * d + 1] * scale_) << 16);
+  }
+
+  __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln, float scale) {
+    scale_ = scale;
+    if constexpr (RES) {
+      // issue the loads of several slots before converting any of them, so
+      // the memory latency is paid a few times per workgroup instead of per slot
+      constexpr int kBatch = NS == 1 ? 8 : 4;
+#pragma unroll
+      for (int i0 = 0; i0 < SPW; i0 += kBatch) {
+        float v[kBatch][8 * NS];
+#pragma unroll
+        for (int bb = 0; bb < kBatch; ++bb) fetch(a, tile, w + NW * (i0 + bb), ln, v[bb], true);
+#pragma unroll
+        for (int bb = 0; bb < kBatch; ++bb) pack(v[bb], areg[i0 + bb]);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
+    const uint4* B = reinterpret_cast<const uint4*>(a.B16);
+    uint4 b[2][NS];
+    float raw[RES ? 1 : 2][RES ? 1 : 8 * NS];
+    auto loadb = [&](int i, uint4 (&dst)[NS]) {
+      const uint4* bp = B + ((size_t)(kt * kSlots + w + NW * i) * (EXACT ? NS : a.NS)) * 64 + ln;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (EXACT || s < a.NS) dst[s] = bp[s * 64];
+    };
+    loadb(0, b[0]);
+    if constexpr (!RES) fetch(a, tile, w, ln, raw[0], false);
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+      u32x4 as[NS];
+      if constexpr (!RES) pack(raw[i % 2], as);
+      if (i + 1 < SPW) {
+        loadb(i + 1, b[(i + 1) % 2]);
+        if constexpr (!RES) fetch(a, tile, w + NW * (i + 1), ln, raw[(i + 1) % 2], false);
+      }
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (EXACT || s < a.NS)
+          acc = Op16<PREC>::mfma(__builtin_bit_cast(V, RES ? areg[RES ? i : 0][s] : as[s]),
+                                 __builtin_bit_cast(V, b[i % 2][s]), acc);
+      store_block(st, w + NW * i, ln, acc);
+    }
+  }
+};
+
+template <int NW>
+struct CorrSmem {
+  float* st;        // [128][2][64][2] spectra of the 64 (row, ref) pairs
+  float2* stc;
+  float* cand_v;    // [NW][64]
+  int* cand_i;
+  float* rb_v;      // [8] running best per row
+  int* rb_i;
+  float2* tw;       // exp(-2 pi i e / 256)
+  int* item;        // batch work item broadcast
+  __device__ __forceinline__ CorrSmem(float* smem) {
+    st = smem;
+    stc = reinterpret_cast<float2*>(smem);
+    cand_v = smem + kSlots * 2 * 64 * 2;
+    cand_i = reinterpret_cast<int*>(cand_v + NW * 64);
+    rb_v = reinterpret_cast<float*>(cand_i + NW * 64);
+    rb_i = reinterpret_cast<int*>(rb_v + 8);
+    tw = reinterpret_cast<float2*>(rb_i + 8);
+    item = reinterpret_cast<int*>(tw + kNphi);
+  }
+  static constexpr size_t bytes() {
+    return (size_t)kSlots * 2 * 64 * 2 * sizeof(float) + 2 * NW * 64 * sizeof(float) + 16 * sizeof(float) +
+           kNphi * sizeof(float2) + 4 * sizeof(int);
+  }
+};
+
+// Power-of-two FP16 scale of chunk row r: |a +- b| <= 2 * 256 * max|pixel|
+// of the row's particle is mapped below 2^14.
+__device__ __forceinline__ float fp16_scale(const CorrArgs& a, int r) {
+  if (r >= a.rows) return 1.f;
+  const float m = fmaxf(a.maxabs[r / a.S] * 512.f, 1e-30f);
+  return ldexpf(1.f, 14 - (int)ceilf(log2f(m)));
+}
+
+// One 8-row tile against every reference tile (see the file comment).
+template <int PREC, int NW, class Contract, bool TABLE>
+__device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const CorrSmem<NW>& sm, Contract& con) {
+  const int tid = threadIdx.x, ln = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (tid < 8) {
+    sm.rb_v[tid] = -INFINITY;
+    sm.rb_i[tid] = 0x7fffffff;
+  }
+  // FP16: the lane's operand row (ln & 7) is scaled by a power of two of its
+  // particle (exact, so results do not depend on how particles are grouped)
+  if constexpr (PREC == kFP32) con.load_a(a, tile, w, ln);
+  else con.load_a(a, tile, w, ln, PREC == kFP16 ? fp16_scale(a, tile * kRowTile + (ln & 7)) : 1.f);
+
+  for (int kt = 0; kt < a.n_ref_tiles; ++kt) {
+    // ---------------- contraction on the matrix cores ----------------
+    con.run(a, sm.st, tile, kt, w, ln);
+    __syncthreads();
+
+    // ---------------- inverse FFT over angle, pass 1 ----------------
+    const int P = ln;
+#pragma unroll 1
+    for (int c = 0; c < 16 / NW; ++c) {
+      const int k2 = w + NW * c;
+      float2 x[16];
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) x[k1] = sm.stc[vidx(16 * k1 + k2, P)];
+      inv_pass1(k2, x, [&](int e) { return sm.tw[e & 255]; });
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) sm.stc[vidx(16 * n1 + k2, P)] = x[n1];
+    }
+    __syncthreads();
+
+    // ---------------- pass 2 + arg-max ----------------
+    const int row_l = P >> 3, ref_l = P & 7;
+    const int row = tile * kRowTile + row_l;
+    const int k = kt * kRefTile + ref_l;
+    // only values above the row's best of earlier reference tiles can win
+    // (a tie with an earlier tile loses: its flat index is smaller)
+    const float thr = sm.rb_v[row_l];
+    float bv = -INFINITY;
+    int bi = 0x7fffffff;
+#pragma unroll 1
+    for (int c = 0; c < 16 / NW; ++c) {
+      const int n1 = w + NW * c;
+      float2 x[16];
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[vidx(16 * n1 + k2, P)];
+      inv_pass2(x);
+      if constexpr (TABLE) {
+        if (row < a.rows && k < a.K) {
+          const int n = row / a.S, s = row - n * a.S;
+          const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
+          for (int m = 0; m < a.M; ++m) {
+            float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
+#pragma unroll
+            for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
+          }
+        }
+      } else {
+        float mx = -INFINITY;
+#pragma unroll
+        for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
+        if (mx > thr && mx >= bv) {
+#pragma unroll
+          for (int n2 = 0; n2 < 16; ++n2) {
+            const int ang = n1 + 16 * n2;
+            if (better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+            if (a.M == 2 && better(x[n2].y, 256 + ang, bv, bi)) { bv = x[n2].y; bi = 256 + ang; }
+          }
+        }
+      }
+    }
+    if constexpr (!TABLE) {
+      sm.cand_v[w * 64 + P] = bv;
+      sm.cand_i[w * 64 + P] = bi;
+    }
+    __syncthreads();
+    if constexpr (!TABLE) {
+      // waves reduce the 8 rows: lane = (wave of origin, ref)
+      for (int r = w; r < kRowTile; r += NW) {
+        const int ww = ln >> 3, ref = ln & 7;
+        const int rr = tile * kRowTile + r;
+        const int kk = kt * kRefTile + ref;
+        float v = -INFINITY;
+        int iota = 0x7fffffff;
+        for (int w2 = ww; w2 < NW; w2 += 8) {
+          const float v2 = sm.cand_v[w2 * 64 + r * 8 + ref];
+          const int li = sm.cand_i[w2 * 64 + r * 8 + ref];
+          if (li != 0x7fffffff && kk < a.K && rr < a.rows) {
+            const int m = li >> 8, ang = li & 255;
+            const int i2 = ((kk * a.M + m) * a.S + rr % a.S) * kNphi + ang;
+            if (better(v2, i2, v, iota)) { v = v2; iota = i2; }
+          }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const float v2 = __shfl_xor(v, o);
+          const int i2 = __shfl_xor(iota, o);
+          if (better(v2, i2, v, iota)) { v = v2; iota = i2; }
+        }
+        if (ln == 0 && iota != 0x7fffffff && better(v, iota, sm.rb_v[r], sm.rb_i[r])) {
+          sm.rb_v[r] = v;
+          sm.rb_i[r] = iota;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!TABLE && tid < 8) {
+    const int r = tile * kRowTile + tid;
+    if (r < a.rows) {
+      const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, r) * a.b_scale) : 1.f;
+      a.row_cc[r] = sm.rb_v[tid] * unscale;
+      a.row_idx[r] = sm.rb_i[tid];
+    }
+  }
+}
+
+template <int PREC, int NW, int MAXR, bool RES, bool EXACT>
+struct ContractFor {
+  typedef typename std::conditional<PREC == kFP32, Fp32Contract<NW, MAXR, RES, EXACT>,
+                                    Half16Contract<PREC == kFP32 ? kBF16 : PREC, NW, MAXR, EXACT, RES>>::type type;
+};
+
+template <int PREC, int NW, int MAXR, bool RES, bool EXACT, bool TABLE>
+__global__ __launch_bounds__(NW * 64) void k_corr(CorrArgs a) {
+  extern __shared__ float smem[];
+  CorrSmem<NW> sm(smem);
+  if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(a.cs32, threadIdx.x);
+  typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
+  corr_tile<PREC, NW, decltype(con), TABLE>(a, blockIdx.x, sm, con);
+}
+
+// Persistent form over the row tiles of several stacks: workgroups pull
+// (stack, tile) items from a counter until all are done.
+template <int PREC, int NW, int MAXR, bool RES, bool EXACT>
+__global__ __launch_bounds__(NW * 64) void k_corr_batch(CorrBatch b) {
+  extern __shared__ float smem[];
+  CorrSmem<NW> sm(smem);
+  if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(b.piece[0].cs32, threadIdx.x);
+  typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) *sm.item = atomicAdd(b.counter, 1);
+    __syncthreads();
+    const int item = *sm.item;
+    if (item >= b.tile_start[b.n]) break;
+    int p = 0;
+    while (p + 1 < b.n && b.tile_start[p + 1] <= item) ++p;
+    corr_tile<PREC, NW, decltype(con), false>(b.piece[p], item - b.tile_start[p], sm, con);
+  }
+}
+
+template <int P_, int NW_, int MR_, bool RES_, bool EXACT_>
+struct Cfg {
+  static constexpr int P = P_, NW = NW_, MR = MR_;
+  static constexpr bool RES = RES_, EXACT = EXACT_;
+};
+
+template <class C>
+inline void launch_one(const CorrArgs& a, bool table, hipStream_t st) {
+  const dim3 grid(a.n_row_tiles), block(C::NW * 64);
+  const size_t lds = CorrSmem<C::NW>::bytes();
+  if (table) hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, true>), grid, block, lds, st, a);
+  else hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, false>), grid, block, lds, st, a);
+}
+
+template <class C>
+inline void launch_one(const CorrBatch& b, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_corr_batch<C::P, C::NW, C::MR, C::RES, C::EXACT>), dim3(grid), dim3(C::NW * 64),
+                     CorrSmem<C::NW>::bytes(), st, b);
+}
+
+// Per-precision instantiation sets (one translation unit each).  `b` null:
+// one launch over a's row tiles (table: write the CC table); else the
+// persistent launch over b's pieces with `grid` workgroups.
+void corr_dispatch_fp32(int variant, int r4min, int r4max, const CorrArgs* a, bool table, const CorrBatch* b,
+                        int grid, hipStream_t st);
+void corr_dispatch_bf16(int variant, int r4min, int r4max, const CorrArgs* a, bool table, const CorrBatch* b,
+                        int grid, hipStream_t st);
+void corr_dispatch_fp16(int variant, int r4min, int r4max, const CorrArgs* a, bool table, const CorrBatch* b,
+                        int grid, hipStream_t st);
+
+template <class C>
+inline void corr_go(const CorrArgs* a, bool table, const CorrBatch* b, int grid, hipStream_t st) {
+  if (b) launch_one<C>(*b, grid, st);
+  else launch_one<C>(*a, table, st);
+}
+
+// 16-bit forms: operand ring bucket MAXR in {8, 12, 16}; exact step count
+// where every work item has the same one.
+template <int PREC, bool RES>
+inline void corr_dispatch_16(int r4min, int r4max, const CorrArgs* a, bool table, const CorrBatch* b, int grid,
+                             hipStream_t st) {
+  const bool ex = (r4min + 7) / 8 == (r4max + 7) / 8;
+  if (r4max <= 8) return corr_go<Cfg<PREC, 8, 8, RES, true>>(a, table, b, grid, st);
+  if (r4max <= 12) {
+    if (ex) return corr_go<Cfg<PREC, 8, 12, RES, true>>(a, table, b, grid, st);
+    return corr_go<Cfg<PREC, 8, 12, RES, false>>(a, table, b, grid, st);
+  }
+  if (ex) return corr_go<Cfg<PREC, 8, 16, RES, true>>(a, table, b, grid, st);
+  return corr_go<Cfg<PREC, 8, 16, RES, false>>(a, table, b, grid, st);
+}
+
+}  // namespace mra

@@ -39,17 +39,19 @@ __device__ __forceinline__ float bilin(const float* img, int o, int Lp, float fx
   return top + fy * (bot - top);
 }
 
+// Workgroup -> item: consecutive items on the same XCD (workgroups are dealt
+// to the 8 XCDs round-robin), so row tiles shared by neighbouring particles
+// are completed in one L2.  The grid is a multiple of 8.
+__device__ __forceinline__ int xcd_item() {
+  const int per_xcd = gridDim.x / 8;
+  return (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+}
+
 template <int MODE>
-__global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float* smem) {
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
   float2* tw = scr + 8 * 64 * 17;  // exp(-2 pi i e / 256), e = 0..255
-  // consecutive particles on the same XCD (workgroups are dealt to the 8
-  // XCDs round-robin), so row tiles shared by neighbours meet in one L2
-  const int per_xcd = gridDim.x / 8;
-  const int n = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (n >= a.n_part) return;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
   if (threadIdx.x < kNphi) tw[threadIdx.x] = w256f(a.cs32, threadIdx.x);
   __syncthreads();
@@ -165,8 +167,33 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
   }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
+  extern __shared__ float smem[];
+  const int n = xcd_item();
+  if (n >= a.n_part) return;
+  polar_particle<MODE>(a, n, smem);
+}
+
+__global__ __launch_bounds__(kPolarThreads) void k_polar_batch(PolarBatch b) {
+  extern __shared__ float smem[];
+  const int item = xcd_item();
+  if (item >= b.start[b.n]) return;
+  int p = 0;
+  while (p + 1 < b.n && b.start[p + 1] <= item) ++p;
+  polar_particle<0>(b.piece[p], item - b.start[p], smem);
+}
+
 size_t polar_lds_bytes(int Lp) {
   return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)(8 * 64 * 17 + kNphi) * sizeof(float2);
+}
+
+hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st) {
+  if (b.n <= 0 || b.start[b.n] <= 0) return hipSuccess;
+  int lp = 0;
+  for (int i = 0; i < b.n; ++i) lp = b.piece[i].Lp > lp ? b.piece[i].Lp : lp;
+  hipLaunchKernelGGL(k_polar_batch, dim3((b.start[b.n] + 7) / 8 * 8), dim3(kPolarThreads), polar_lds_bytes(lp), st, b);
+  return hipGetLastError();
 }
 
 hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
@@ -185,11 +212,9 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
 // sum_r w_r sum_j p_{s,m}[r][j] * qhat_k[r][(j + a) mod 256] with a = -psi.
 // The mirrored samples are the unmirrored stencil read at angle -j (the
 // stencil table is built symmetric in j <-> 256 - j).
-__global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, float* smem) {
   float* img = smem;
-  __shared__ double red[256];
-  const int n = blockIdx.x;
+  double* red = reinterpret_cast<double*>(smem + ((a.Lp * a.Lp + 1) & ~1));
   const int64_t gi = a.out_off + n;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
   __syncthreads();
@@ -220,29 +245,51 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
   if (j == 0) a.cc[gi] = (float)red[0];
 }
 
+static size_t rescore_lds_bytes(int Lp) { return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + 256 * sizeof(double); }
+
+__global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
+  extern __shared__ float smem[];
+  rescore_particle(a, blockIdx.x, smem);
+}
+
+__global__ __launch_bounds__(256) void k_rescore_batch(RescoreBatch b) {
+  extern __shared__ float smem[];
+  const int item = blockIdx.x;
+  int p = 0;
+  while (p + 1 < b.n && b.start[p + 1] <= item) ++p;
+  rescore_particle(b.piece[p], item - b.start[p], smem);
+}
+
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t st) {
   if (a.n_part <= 0) return hipSuccess;
-  const size_t lds = (size_t)a.Lp * a.Lp * sizeof(float);
-  hipLaunchKernelGGL(k_rescore, dim3(a.n_part), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(k_rescore, dim3(a.n_part), dim3(256), rescore_lds_bytes(a.Lp), st, a);
   return hipGetLastError();
 }
 
-// max |x| over n floats into *out (which the caller zeroes); non-negative
-// floats order like their bit patterns, so an integer atomic max suffices.
-__global__ __launch_bounds__(256) void k_maxabs(const float* x, int64_t n, float* out) {
-  float m = 0.f;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    m = fmaxf(m, fabsf(x[i]));
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(m));
+hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st) {
+  if (b.n <= 0 || b.start[b.n] <= 0) return hipSuccess;
+  int lp = 0;
+  for (int i = 0; i < b.n; ++i) lp = b.piece[i].Lp > lp ? b.piece[i].Lp : lp;
+  hipLaunchKernelGGL(k_rescore_batch, dim3(b.start[b.n]), dim3(256), rescore_lds_bytes(lp), st, b);
+  return hipGetLastError();
 }
 
-hipError_t launch_maxabs(const float* x, int64_t n, float* out, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_maxabs, dim3(blocks), dim3(256), 0, st, x, n, out);
+// max |pixel| of each particle image (the FP16 operand scale): one
+// workgroup per particle, out[n] for n < n_part.
+__global__ __launch_bounds__(256) void k_part_maxabs(const float* x, int LL, float* out) {
+  __shared__ float red[4];
+  const float* img = x + (size_t)blockIdx.x * LL;
+  float m = 0.f;
+  for (int i = threadIdx.x; i < LL; i += 256) m = fmaxf(m, fabsf(img[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+hipError_t launch_part_maxabs(const float* x, int n_part, int L, float* out, hipStream_t st) {
+  if (n_part <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_part_maxabs, dim3(n_part), dim3(256), 0, st, x, L * L, out);
   return hipGetLastError();
 }
 

@@ -34,6 +34,8 @@ struct Refset {
   Stencil* stencil = nullptr;
   float b_scale = 1.f;
   int dmin = 0, dmax = 0;  // range of stencil floor offsets
+  int variant = 0;         // correlation kernel tile configuration
+  int chunk = 0;           // particles per chunk (0: from the workspace cap)
 };
 
 struct Fail {
@@ -53,6 +55,8 @@ struct mra_ctx {
   double2* cs64 = nullptr;
   float2* cs32 = nullptr;
   std::map<std::string, DevBuf> ws;
+  int n_cu = 256;
+  int* counter = nullptr;  // work-item counter of persistent launches
   bool profiling = false;
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
 };
@@ -193,6 +197,7 @@ void check_result(const mra_result* r) {
 size_t a_bytes_per_row(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * sizeof(float) / kRowTile; }
 
 int64_t chunk_particles(mra_ctx* c, const Refset& rs, const Plan& p) {
+  if (rs.chunk > 0) return rs.chunk;
   const uint64_t budget = std::max<uint64_t>(c->cap / 2, 64ull << 20);
   const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
   int64_t n = (int64_t)(budget / per);
@@ -217,9 +222,8 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
 
   float* maxabs = nullptr;
   if (rs.g.precision == kFP16) {
-    maxabs = (float*)ws_get(c, "maxabs", 256);
-    hip_check(c, hipMemsetAsync(maxabs, 0, sizeof(float), st), "memset");
-    timed(c, "maxabs", [&] { hip_check(c, launch_maxabs(src, (int64_t)nc * L * L, maxabs, st), "maxabs"); });
+    maxabs = (float*)ws_get(c, "maxabs", (size_t)nc * sizeof(float));
+    timed(c, "maxabs", [&] { hip_check(c, launch_part_maxabs(src, nc, L, maxabs, st), "maxabs"); });
   }
 
   PolarArgs pa{};
@@ -245,7 +249,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.row_cc = rcc;
   ca.row_idx = ridx;
   ca.table = table;
-  timed(c, "corr", [&] { hip_check(c, launch_corr(rs.g.precision, table != nullptr, ca, st), "corr"); });
+  timed(c, "corr", [&] { hip_check(c, launch_corr(rs.g.precision, rs.variant, table != nullptr, ca, st), "corr"); });
   if (table) return;
 
   MergeArgs ma{};
@@ -287,6 +291,140 @@ void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, co
     float* tab = table ? table + (size_t)n0 * rs.K * p.M * p.S * kNphi : nullptr;
     run_chunk(c, rs, p, parts, n0, nc, out, tab);
   }
+}
+
+// One piece of a stack inside a batched wave.
+struct Piece {
+  int stack;
+  const Refset* rs;
+  Plan p;
+  int64_t n0;
+  int nc;
+  size_t a_off;  // first float of the piece in the wave's A buffer
+  size_t row0;   // first row in the wave's row-result buffers
+};
+
+void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
+  hipStream_t st = c->stream;
+  const Refset& rs0 = *w[0].rs;
+  const int prec = rs0.g.precision, variant = rs0.variant;
+  size_t a_floats = 0, rows = 0, part_total = 0;
+  for (Piece& pc : w) {
+    part_total += pc.nc;
+    pc.a_off = a_floats;
+    pc.row0 = rows;
+    const size_t r = (size_t)pc.nc * pc.p.S;
+    a_floats += (r + kRowTile - 1) / kRowTile * (size_t)kSlots * pc.rs->R4 * 64;
+    rows += r;
+  }
+  float* A = (float*)ws_get(c, "A", a_floats * sizeof(float));
+  float* rcc = (float*)ws_get(c, "row_cc", rows * sizeof(float));
+  int* ridx = (int*)ws_get(c, "row_idx", rows * sizeof(int));
+  float* maxabs = prec == kFP16 ? (float*)ws_get(c, "maxabs", (size_t)part_total * sizeof(float)) : nullptr;
+
+  PolarBatch pb{};
+  CorrBatch cb{};
+  MergeBatch mb{};
+  RescoreBatch rb{};
+  pb.n = cb.n = mb.n = rb.n = (int)w.size();
+  cb.counter = c->counter;
+  int part = 0, tile = 0;
+  for (size_t i = 0; i < w.size(); ++i) {
+    const Piece& pc = w[i];
+    const Refset& rs = *pc.rs;
+    const mra_stack& sk = stacks[pc.stack];
+    const int L = rs.g.L;
+    const int prow = pc.nc * pc.p.S;
+    const int ptiles = (prow + kRowTile - 1) / kRowTile;
+    const size_t tile_floats = (size_t)kSlots * rs.R4 * 64;
+    float* Ap = A + pc.a_off;
+    const float* src = sk.parts + (size_t)pc.n0 * L * L;
+    if (prow % kRowTile)
+      hip_check(c, hipMemsetAsync(Ap + (size_t)(ptiles - 1) * tile_floats, 0, tile_floats * sizeof(float), st), "memset");
+    float* mx = nullptr;
+    if (maxabs) {
+      mx = maxabs + part;
+      timed(c, "maxabs", [&] { hip_check(c, launch_part_maxabs(src, pc.nc, L, mx, st), "maxabs"); });
+    }
+    PolarArgs& pa = pb.piece[i];
+    pa.parts = src; pa.n_part = pc.nc;
+    pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = pc.p.T; pa.S1 = pc.p.S1; pa.S = pc.p.S;
+    pa.Lp = pc.p.Lp; pa.pad = pc.p.pad; pa.cx = pc.p.cx; pa.stencil = rs.stencil; pa.cs32 = c->cs32; pa.out = Ap;
+    pb.start[i] = part;
+
+    CorrArgs& ca = cb.piece[i];
+    ca.A = Ap; ca.n_row_tiles = ptiles; ca.rows = prow;
+    ca.B32 = rs.B32; ca.B16 = rs.B16;
+    ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = pc.p.S; ca.M = pc.p.M;
+    ca.maxabs = mx; ca.b_scale = rs.b_scale; ca.cs32 = c->cs32;
+    ca.row_cc = rcc + pc.row0; ca.row_idx = ridx + pc.row0; ca.table = nullptr;
+    cb.tile_start[i] = tile;
+
+    MergeArgs& ma = mb.piece[i];
+    ma.row_cc = rcc + pc.row0; ma.row_idx = ridx + pc.row0;
+    ma.n_part = pc.nc; ma.S = pc.p.S; ma.S1 = pc.p.S1; ma.T = pc.p.T; ma.M = pc.p.M; ma.out_off = pc.n0;
+    ma.ref = sk.out.ref; ma.shift_x = sk.out.shift_x; ma.shift_y = sk.out.shift_y; ma.psi = sk.out.psi;
+    ma.mirror = sk.out.mirror; ma.flat = sk.out.flat_index; ma.cc = sk.out.cc; ma.cc2 = sk.out.cc2;
+    mb.start[i] = part;
+
+    RescoreArgs& ra = rb.piece[i];
+    ra.parts = src; ra.n_part = pc.nc; ra.out_off = pc.n0;
+    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = pc.p.Lp; ra.pad = pc.p.pad; ra.cx = pc.p.cx;
+    ra.K = rs.K; ra.T = pc.p.T; ra.stencil = rs.stencil; ra.qhat = rs.qhat;
+    ra.ref = sk.out.ref; ra.shift_x = sk.out.shift_x; ra.shift_y = sk.out.shift_y; ra.psi = sk.out.psi;
+    ra.mirror = sk.out.mirror; ra.cc = sk.out.cc;
+    rb.start[i] = part;
+
+    part += pc.nc;
+    tile += ptiles;
+  }
+  pb.start[w.size()] = mb.start[w.size()] = rb.start[w.size()] = part;
+  cb.tile_start[w.size()] = tile;
+  timed(c, "polar", [&] { hip_check(c, launch_polar_batch(pb, st), "polar batch"); });
+  hip_check(c, hipMemsetAsync(c->counter, 0, sizeof(int), st), "memset");
+  const int grid = std::min(tile, c->n_cu);
+  timed(c, "corr", [&] { hip_check(c, launch_corr_batch(prec, variant, cb, grid, st), "corr batch"); });
+  timed(c, "merge", [&] { hip_check(c, launch_merge_batch(mb, st), "merge batch"); });
+  if (prec != kFP32) timed(c, "rescore", [&] { hip_check(c, launch_rescore_batch(rb, st), "rescore batch"); });
+}
+
+void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Plan>& plans) {
+  const uint64_t budget = std::max<uint64_t>(c->cap / 2, 64ull << 20);
+  // stacks that share a correlation instantiation (precision, tile variant)
+  // are packed into the same waves; within a group the caller's order holds
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto key = [&](int i) {
+    if (stacks[i].N <= 0) return 0;
+    const Refset& rs = get_refset(c, stacks[i].refset_id);
+    return rs.g.precision * 16 + rs.variant;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+  std::vector<Piece> wave;
+  uint64_t used = 0;
+  for (int i : order) {
+    const mra_stack& s = stacks[i];
+    if (s.N <= 0) continue;
+    const Refset& rs = get_refset(c, s.refset_id);
+    const Plan& p = plans[i];
+    const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
+    const int64_t cap_n = rs.chunk > 0 ? rs.chunk : std::max<int64_t>(1, (int64_t)(budget / per));
+    for (int64_t n0 = 0; n0 < s.N;) {
+      const bool compatible = wave.empty() || (wave[0].rs->g.precision == rs.g.precision &&
+                                               wave[0].rs->variant == rs.variant);
+      if (!compatible || (int)wave.size() == kMaxBatchPieces || used + per > budget) {
+        if (!wave.empty()) launch_wave(c, stacks, wave);
+        wave.clear();
+        used = 0;
+      }
+      const int64_t room = std::max<int64_t>(1, (int64_t)((budget - used) / per));
+      const int nc = (int)std::min<int64_t>({s.N - n0, room, cap_n, (int64_t)(INT32_MAX / p.S / 2)});
+      wave.push_back(Piece{i, &rs, p, n0, nc, 0, 0});
+      used += (uint64_t)nc * per + (uint64_t)kRowTile * a_bytes_per_row(rs);
+      n0 += nc;
+    }
+  }
+  if (!wave.empty()) launch_wave(c, stacks, wave);
 }
 
 template <class F>
@@ -338,6 +476,10 @@ int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_c
       h64[j] = make_double2(cs[j], sn[j]);
       h32[j] = make_float2((float)cs[j], (float)sn[j]);
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+      c->n_cu = ncu;
+    c->counter = (int*)alloc(c, 256, "counter");
     c->cs64 = (double2*)alloc(c, kNphi * sizeof(double2), "cs64");
     c->cs32 = (float2*)alloc(c, kNphi * sizeof(float2), "cs32");
     hip_check(c, hipMemcpy(c->cs64, h64.data(), kNphi * sizeof(double2), hipMemcpyHostToDevice), "memcpy");
@@ -359,6 +501,7 @@ int mra_destroy(mra_ctx* c) {
   for (auto& kv : c->refs) free_refset(kv.second);
   for (auto& kv : c->ws)
     if (kv.second.p) (void)hipFree(kv.second.p);
+  if (c->counter) (void)hipFree(c->counter);
   if (c->cs64) (void)hipFree(c->cs64);
   if (c->cs32) (void)hipFree(c->cs32);
   delete c;
@@ -377,6 +520,7 @@ int mra_load_refs(mra_ctx* c, int32_t id, const float* refs, int32_t K, const mr
     rs.R4 = (rs.R + 3) / 4;
     rs.NS = (rs.R4 + 7) / 8;
     rs.n_kt = (K + kRefTile - 1) / kRefTile;
+    rs.variant = corr_default_variant(g->precision, rs.R4);
     hipStream_t st = c->stream;
     try {
       // particle sampling stencil, exactly symmetric in j <-> 256 - j
@@ -474,18 +618,19 @@ int mra_align(mra_ctx* c, int32_t id, const float* parts, int64_t N, mra_result*
 int mra_align_batch(mra_ctx* c, const mra_stack* stacks, int32_t n) {
   return guard(c, [&] {
     if (n < 0 || (n > 0 && !stacks)) throw Fail{MRA_E_INVAL, "bad stack list"};
+    std::vector<Plan> plans(n);
     for (int i = 0; i < n; ++i) {  // validate everything before enqueueing anything
       const mra_stack& s = stacks[i];
       Refset& rs = get_refset(c, s.refset_id);
       if (s.N < 0) throw Fail{MRA_E_INVAL, "stack N must be >= 0"};
+      plans[i] = plan_for(rs, s.shift_max < 0 ? rs.g.shift_max : s.shift_max);
       if (s.N > 0) {
         if (!s.parts) throw Fail{MRA_E_INVAL, "stack parts is NULL"};
         check_result(&s.out);
-        plan_for(rs, s.shift_max < 0 ? rs.g.shift_max : s.shift_max);
+        if (s.N * (int64_t)plans[i].S > INT32_MAX / 2) throw Fail{MRA_E_INVAL, "stack too large"};
       }
     }
-    for (int i = 0; i < n; ++i)
-      align_impl(c, stacks[i].refset_id, stacks[i].parts, stacks[i].N, stacks[i].shift_max, &stacks[i].out, nullptr);
+    run_batch(c, stacks, n, plans);
   });
 }
 
@@ -565,6 +710,27 @@ int mra_debug_refs(mra_ctx* c, int32_t id, float* qhat, double* norm) {
       hip_check(c, hipMemcpyAsync(qhat, rs.qhat, (size_t)rs.K * rs.R * kNphi * sizeof(float), hipMemcpyDeviceToDevice, c->stream), "memcpy");
     if (norm)
       hip_check(c, hipMemcpyAsync(norm, rs.norm, (size_t)rs.K * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "memcpy");
+  });
+}
+
+int mra_set_tuning(mra_ctx* c, int32_t id, const mra_tuning* t) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (!t) throw Fail{MRA_E_INVAL, "tuning is NULL"};
+    const int v = t->corr_variant < 0 ? corr_default_variant(rs.g.precision, rs.R4) : t->corr_variant;
+    if (!corr_variant_ok(rs.g.precision, v, rs.R4)) throw Fail{MRA_E_INVAL, "variant cannot serve this geometry"};
+    if (t->chunk_particles < 0) throw Fail{MRA_E_INVAL, "chunk_particles must be >= 0"};
+    rs.variant = v;
+    rs.chunk = t->chunk_particles;
+  });
+}
+
+int mra_get_tuning(mra_ctx* c, int32_t id, mra_tuning* t) {
+  return guard(c, [&] {
+    Refset& rs = get_refset(c, id);
+    if (!t) throw Fail{MRA_E_INVAL, "tuning is NULL"};
+    t->corr_variant = rs.variant;
+    t->chunk_particles = rs.chunk;
   });
 }
 

@@ -13,7 +13,7 @@ constexpr int kSlots = 128;         // frequency slots: f = 1..127, slot 0 = (f 
 constexpr int kRowTile = 8;         // particle rows (shift, particle) per correlation tile
 constexpr int kRefTile = 8;         // references per correlation tile
 constexpr int kPolarThreads = 512;  // 8 waves: one ring per wave, 8 shifts x 8 FFT lanes
-constexpr int kCorrThreads = 512;   // 8 waves
+constexpr int kMaxBatchPieces = 12; // stack pieces per batched launch (kernel-argument table)
 constexpr int kAvgChunk = 64;       // particles per partial class sum
 constexpr int kAvgThreads = 256;
 
@@ -50,12 +50,21 @@ struct CorrArgs {
   const float* B32;      // [ref tiles][128][R4][64]
   const uint16_t* B16;   // [ref tiles][128][NS][64][8]
   int R, R4, NS, n_ref_tiles, K, S, M;
-  const float* maxabs;   // FP16: device max |pixel| of the chunk (A scale), else null
+  const float* maxabs;   // FP16: max |pixel| of each particle of the chunk (A scale), else null
   float b_scale;         // FP16: power-of-two scale folded into B16
   const float2* cs32;
   float* row_cc;         // [rows] best CC of the row
   int* row_idx;          // [rows] flat index of the row's best
   float* table;          // debug: [n][K][M][S][256], else null
+};
+
+// Batched correlation: pieces of several stacks in one persistent launch.
+// tile_start[i] is the first work item of piece i; tile_start[n] the total.
+struct CorrBatch {
+  int n;
+  int* counter;          // zeroed before the launch
+  int tile_start[kMaxBatchPieces + 1];
+  CorrArgs piece[kMaxBatchPieces];
 };
 
 struct MergeArgs {
@@ -78,13 +87,37 @@ struct RescoreArgs {
   float* cc;
 };
 
+// Batched forms of the per-particle kernels: item i of the launch is
+// particle i - start[p] of piece p with start[p] <= i < start[p + 1].
+struct PolarBatch {
+  int n;
+  int start[kMaxBatchPieces + 1];
+  PolarArgs piece[kMaxBatchPieces];
+};
+struct MergeBatch {
+  int n;
+  int start[kMaxBatchPieces + 1];
+  MergeArgs piece[kMaxBatchPieces];
+};
+struct RescoreBatch {
+  int n;
+  int start[kMaxBatchPieces + 1];
+  RescoreArgs piece[kMaxBatchPieces];
+};
+
 // ---- launchers (one .hip file each) ----
 hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st);
 size_t polar_lds_bytes(int Lp);
-hipError_t launch_corr(int prec, bool table, const CorrArgs& a, hipStream_t st);
+hipError_t launch_corr(int prec, int variant, bool table, const CorrArgs& a, hipStream_t st);
+hipError_t launch_corr_batch(int prec, int variant, const CorrBatch& b, int grid, hipStream_t st);
+bool corr_variant_ok(int prec, int variant, int R4);
+int corr_default_variant(int prec, int R4);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t st);
 hipError_t launch_rescore(const RescoreArgs& a, hipStream_t st);
-hipError_t launch_maxabs(const float* x, int64_t n, float* out, hipStream_t st);
+hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st);
+hipError_t launch_merge_batch(const MergeBatch& b, hipStream_t st);
+hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st);
+hipError_t launch_part_maxabs(const float* x, int n_part, int L, float* out, hipStream_t st);
 
 // reference preparation
 struct RefArgs {

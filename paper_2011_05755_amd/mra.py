@@ -21,7 +21,8 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = (
     "mra_create", "mra_destroy", "mra_load_refs", "mra_unload_refs", "mra_refset_info",
-    "mra_align", "mra_update_averages", "mra_align_batch", "mra_debug_polar",
+    "mra_align", "mra_update_averages", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
+    "mra_debug_polar",
     "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_profile", "mra_profile_read",
     "mra_last_error", "mra_strerror",
 )
@@ -41,6 +42,10 @@ class Result(ctypes.Structure):
 class Stack(ctypes.Structure):
     _fields_ = [("refset_id", ctypes.c_int32), ("parts", ctypes.c_void_p), ("N", ctypes.c_int64),
                 ("shift_max", ctypes.c_int32), ("out", Result)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("corr_variant", ctypes.c_int32), ("chunk_particles", ctypes.c_int32)]
 
 
 class MRAError(RuntimeError):
@@ -70,6 +75,8 @@ def load_library() -> ctypes.CDLL:
         "mra_align": [vp, i32, vp, i64, ctypes.POINTER(Result)],
         "mra_update_averages": [vp, i32, vp, i64, ctypes.POINTER(Result), vp, vp],
         "mra_align_batch": [vp, ctypes.POINTER(Stack), i32],
+        "mra_set_tuning": [vp, i32, ctypes.POINTER(Tuning)],
+        "mra_get_tuning": [vp, i32, ctypes.POINTER(Tuning)],
         "mra_debug_polar": [vp, i32, vp, i64, vp],
         "mra_debug_spectra": [vp, i32, vp, i64, vp],
         "mra_debug_cctable": [vp, i32, vp, i64, vp],
@@ -238,6 +245,16 @@ class Context:
         self._check(self.lib.mra_update_averages(self._h, refset_id, _ptr(parts), parts.shape[0],
                                                  ctypes.byref(p), _ptr(averages), _ptr(counts)))
         return counts
+
+    # ---- tile configuration (see include/mra.h, mra_tuning) ----
+    def set_tuning(self, refset_id: int, corr_variant: int = -1, chunk_particles: int = 0):
+        t = Tuning(corr_variant, chunk_particles)
+        self._check(self.lib.mra_set_tuning(self._h, refset_id, ctypes.byref(t)))
+
+    def get_tuning(self, refset_id: int) -> tuple[int, int]:
+        t = Tuning()
+        self._check(self.lib.mra_get_tuning(self._h, refset_id, ctypes.byref(t)))
+        return t.corr_variant, t.chunk_particles
 
     # ---- kernel timing ----
     def profile(self, enable: bool):
