@@ -84,10 +84,20 @@ __device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int 
   const int R4 = RX > 0 ? RX : a.R4;
   return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
 }
+// Element t of the lane's operand: ring (ln/16)*R4 + t.  The load is never
+// conditional (a conditional load waits for its data before the next one is
+// issued): its element index is clamped into the slot's block, and elements
+// t >= R4 and padding rings >= R (which hold no data) are cleared by an AND
+// with a mask that is opaque to the optimiser, which would otherwise turn
+// the select back into a branch around the load.
 template <int RX = 0>
-__device__ __forceinline__ bool ring_ok(const CorrArgs& a, int ln, int t) {
+__device__ __forceinline__ float a_elem(const CorrArgs& a, const float* ap, int ln, int t, bool nt) {
   const int R4 = RX > 0 ? RX : a.R4;
-  return t < R4 && (ln >> 4) * R4 + t < a.R;
+  const int tt = t < R4 ? t : R4 - 1;
+  const float x = nt ? __builtin_nontemporal_load(ap + tt * 16) : ap[tt * 16];
+  uint32_t keep = (t < R4 && (ln >> 4) * R4 + t < a.R) ? 0xffffffffu : 0u;
+  asm("" : "+v"(keep));
+  return __uint_as_float(__float_as_uint(x) & keep);
 }
 
 // store a 16x16 MFMA block of slot `slot` into the LDS spectrum state
@@ -118,54 +128,68 @@ struct Fp32Contract {
       for (int i = 0; i < SPW; ++i) {
         const float* ap = a_lane<RX>(a, tile, w + NW * i, ln);
 #pragma unroll
-        for (int t = 0; t < MAXR; ++t) areg[i][t] = ring_ok<RX>(a, ln, t) ? __builtin_nontemporal_load(ap + t * 16) : 0.f;
+        for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<RX>(a, ap, ln, t, true);
       }
     }
   }
 
   __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
-    float b[4][MAXR];
-    float av[4][RES ? 1 : MAXR];
+    const int R4 = EXACT ? MAXR : a.R4;
     auto loadb = [&](int i, float (&dst)[MAXR]) {
-      const float* bp = a.B32 + ((size_t)(kt * kSlots + w + NW * i) * (EXACT ? MAXR : a.R4)) * 64 + ln;
+      const float* bp = a.B32 + ((size_t)(kt * kSlots + w + NW * i) * R4) * 64 + ln;
 #pragma unroll
-      for (int t = 0; t < MAXR; ++t)
-        if (EXACT || t < a.R4) dst[t] = bp[t * 64];
+      for (int t = 0; t < MAXR; ++t) dst[t] = bp[(t < R4 ? t : R4 - 1) * 64];  // unconditional
     };
-    auto loada = [&](int i, float (&dst)[RES ? 1 : MAXR]) {
-      if constexpr (!RES) {
+    if constexpr (RES) {
+      // slots in pairs: two independent accumulation chains keep the matrix
+      // pipe busy; the reference operand of the next pair is in flight
+      float b[4][MAXR];
+      loadb(0, b[0]);
+      loadb(1, b[1]);
+#pragma unroll
+      for (int i = 0; i < SPW; i += 2) {
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < MAXR; ++t) {
+          if (t < R4) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[i][t], b[i % 4][t], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[i + 1][t], b[(i + 1) % 4][t], acc1, 0, 0, 0);
+          }
+        }
+        if (i + 2 < SPW) loadb(i + 2, b[(i + 2) % 4]);
+        if (i + 3 < SPW) loadb(i + 3, b[(i + 3) % 4]);
+        store_block(st, w + NW * i, ln, acc0);
+        store_block(st, w + NW * (i + 1), ln, acc1);
+      }
+    } else {
+      // both operands streamed, one slot ahead (explicit double buffer so
+      // that the slot loop need not be unrolled)
+      float b0[MAXR], a0[MAXR], b1[MAXR], a1[MAXR];
+      auto loada = [&](int i, float (&dst)[MAXR]) {
         const float* ap = a_lane<RX>(a, tile, w + NW * i, ln);
 #pragma unroll
-        for (int t = 0; t < MAXR; ++t) dst[t] = ring_ok<RX>(a, ln, t) ? ap[t * 16] : 0.f;
-      }
-    };
-    loadb(0, b[0]);
-    loada(0, av[0]);
-    loadb(1, b[1]);
-    loada(1, av[1]);
+        for (int t = 0; t < MAXR; ++t) dst[t] = a_elem<RX>(a, ap, ln, t, false);
+      };
+      auto chain = [&](const float (&x)[MAXR], const float (&y)[MAXR], int slot) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < SPW; i += 2) {
-      // two independent accumulation chains keep the matrix pipe busy
-      f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < MAXR; ++t) {
-        if (EXACT || t < a.R4) {
-          const float x0 = RES ? areg[i][RES ? t : 0] : av[i % 4][RES ? 0 : t];
-          const float x1 = RES ? areg[i + 1][RES ? t : 0] : av[(i + 1) % 4][RES ? 0 : t];
-          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, b[i % 4][t], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, b[(i + 1) % 4][t], acc1, 0, 0, 0);
+        for (int t = 0; t < MAXR; ++t)
+          if (t < R4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t], y[t], acc, 0, 0, 0);
+        store_block(st, slot, ln, acc);
+      };
+      loadb(0, b0);
+      loada(0, a0);
+#pragma unroll 1
+      for (int i = 0; i < SPW; i += 2) {
+        loadb(i + 1, b1);
+        loada(i + 1, a1);
+        chain(a0, b0, w + NW * i);
+        if (i + 2 < SPW) {
+          loadb(i + 2, b0);
+          loada(i + 2, a0);
         }
+        chain(a1, b1, w + NW * (i + 1));
       }
-      if (i + 2 < SPW) {
-        loadb(i + 2, b[(i + 2) % 4]);
-        loada(i + 2, av[(i + 2) % 4]);
-      }
-      if (i + 3 < SPW) {
-        loadb(i + 3, b[(i + 3) % 4]);
-        loada(i + 3, av[(i + 3) % 4]);
-      }
-      store_block(st, w + NW * i, ln, acc0);
-      store_block(st, w + NW * (i + 1), ln, acc1);
     }
   }
 };
@@ -186,8 +210,7 @@ struct Half16Contract {
   __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, float (&v)[8 * NS], bool nt) {
     const float* ap = a_lane(a, tile, slot, ln);
 #pragma unroll
-    for (int t = 0; t < 8 * NS; ++t)
-      v[t] = (t < MAXR && ring_ok(a, ln, t)) ? (nt ? __builtin_nontemporal_load(ap + t * 16) : ap[t * 16]) : 0.f;
+    for (int t = 0; t < 8 * NS; ++t) v[t] = t < MAXR ? a_elem(a, ap, ln, t, nt) : 0.f;
   }
   __device__ __forceinline__ void pack(const float (&v)[8 * NS], u32x4 (&dst)[NS]) const {
 #pragma unroll
@@ -215,31 +238,47 @@ struct Half16Contract {
 
   __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
     const uint4* B = reinterpret_cast<const uint4*>(a.B16);
-    uint4 b[2][NS];
-    float raw[RES ? 1 : 2][RES ? 1 : 8 * NS];
+    const int ns = EXACT ? NS : a.NS;
     auto loadb = [&](int i, uint4 (&dst)[NS]) {
-      const uint4* bp = B + ((size_t)(kt * kSlots + w + NW * i) * (EXACT ? NS : a.NS)) * 64 + ln;
+      const uint4* bp = B + ((size_t)(kt * kSlots + w + NW * i) * ns) * 64 + ln;
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (EXACT || s < a.NS) dst[s] = bp[s * 64];
+      for (int s = 0; s < NS; ++s) dst[s] = bp[(s < ns ? s : ns - 1) * 64];  // unconditional
     };
-    loadb(0, b[0]);
-    if constexpr (!RES) fetch(a, tile, w, ln, raw[0], false);
-#pragma unroll
-    for (int i = 0; i < SPW; ++i) {
-      u32x4 as[NS];
-      if constexpr (!RES) pack(raw[i % 2], as);
-      if (i + 1 < SPW) {
-        loadb(i + 1, b[(i + 1) % 2]);
-        if constexpr (!RES) fetch(a, tile, w + NW * (i + 1), ln, raw[(i + 1) % 2], false);
-      }
+    auto chain = [&](const u32x4 (&x)[NS], const uint4 (&y)[NS], int slot) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NS; ++s)
-        if (EXACT || s < a.NS)
-          acc = Op16<PREC>::mfma(__builtin_bit_cast(V, RES ? areg[RES ? i : 0][s] : as[s]),
-                                 __builtin_bit_cast(V, b[i % 2][s]), acc);
-      store_block(st, w + NW * i, ln, acc);
+        if (s < ns) acc = Op16<PREC>::mfma(__builtin_bit_cast(V, x[s]), __builtin_bit_cast(V, y[s]), acc);
+      store_block(st, slot, ln, acc);
+    };
+    if constexpr (RES) {
+      uint4 b[2][NS];
+      loadb(0, b[0]);
+#pragma unroll
+      for (int i = 0; i < SPW; ++i) {
+        if (i + 1 < SPW) loadb(i + 1, b[(i + 1) % 2]);
+        chain(areg[RES ? i : 0], b[i % 2], w + NW * i);
+      }
+    } else {
+      // explicit double buffer so that the slot loop need not be unrolled
+      uint4 b0[NS], b1[NS];
+      float r0[8 * NS], r1[8 * NS];
+      u32x4 x[NS];
+      loadb(0, b0);
+      fetch(a, tile, w, ln, r0, false);
+#pragma unroll 1
+      for (int i = 0; i < SPW; i += 2) {
+        loadb(i + 1, b1);
+        fetch(a, tile, w + NW * (i + 1), ln, r1, false);
+        pack(r0, x);
+        chain(x, b0, w + NW * i);
+        if (i + 2 < SPW) {
+          loadb(i + 2, b0);
+          fetch(a, tile, w + NW * (i + 2), ln, r0, false);
+        }
+        pack(r1, x);
+        chain(x, b1, w + NW * (i + 1));
+      }
     }
   }
 };
