@@ -34,6 +34,11 @@ FP32_MATRIX_PEAK = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 BF16_MATRIX_PEAK = 2500.0  # TFLOP/s, dense
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector (published)
 HBM_PEAK = 8000.0          # GB/s
+# HBM bytes per launch of the FP32 correlation kernel on this workload, from
+# FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) counters calibrated on a 1 GiB
+# copy (profiles/mra_c1_hbm_traffic.md).  Set to None when the kernel changes
+# until the counters are taken again.
+CORR_FP32_TRAFFIC_BYTES = 5.045e9
 
 
 def log(msg):
@@ -60,6 +65,9 @@ def main() -> int:
     ap.add_argument("--forms", default="fp32,bf16")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reads and writes MIB MiB), "
+                         "a reference for hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -70,6 +78,15 @@ def main() -> int:
     from paper_2011_05755_amd import mra, synth
 
     dev = torch.device("cuda", 0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 18          # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del src, dst
     w = synth.WORKLOADS["mra_c1"]
     N, L, K, T, r_min, r_max = w["N"], w["L"], w["K"], w["shift_max"], w["r_min"], w["r_max"]
     R = r_max - r_min + 1
@@ -117,7 +134,9 @@ def main() -> int:
     achieved = corr_flops / (corr_ms / 1000.0) / 1e12
     peak = FP32_MATRIX_PEAK if head == "fp32" else BF16_MATRIX_PEAK
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=None,
+                    frac=round(achieved / peak, 4),
+                    traffic=CORR_FP32_TRAFFIC_BYTES if head == "fp32" else None,
+                    traffic_unit="bytes per launch (HBM, counter-measured)",
                     kernel="k_corr", launches_per_step=corr_n // args.steps,
                     avg_launch_ms=round(corr_ms / corr_n, 4),
                     flops_per_row_ref=corr_flops_per_row_ref(R))
