@@ -451,23 +451,29 @@ __global__ __launch_bounds__(NW * 64) void k_corr(CorrArgs a) {
   corr_tile<PREC, NW, decltype(con), TABLE>(a, blockIdx.x, sm, con);
 }
 
-// Persistent form over the row tiles of several stacks: workgroups pull
-// (stack, tile) items from a counter until all are done.
+// Persistent form over the row tiles of several stacks.  Workgroup g takes
+// item g first, then items gridDim.x + counter++ until all are done; the
+// next item is requested while the current one runs, so the counter's
+// latency is hidden.  Every workgroup exits once an item is past the end
+// (the counter only grows), and *counter must be 0 at launch.
 template <int PREC, int NW, int MAXR, bool RES, bool EXACT>
 __global__ __launch_bounds__(NW * 64) void k_corr_batch(CorrBatch b) {
   extern __shared__ float smem[];
   CorrSmem<NW> sm(smem);
   if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(b.piece[0].cs32, threadIdx.x);
   typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) *sm.item = atomicAdd(b.counter, 1);
-    __syncthreads();
-    const int item = *sm.item;
-    if (item >= b.tile_start[b.n]) break;
+  const int total = b.tile_start[b.n];
+  int item = blockIdx.x;
+  while (item < total) {
+    int next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(b.counter, 1) + (int)gridDim.x;
     int p = 0;
     while (p + 1 < b.n && b.tile_start[p + 1] <= item) ++p;
     corr_tile<PREC, NW, decltype(con), false>(b.piece[p], item - b.tile_start[p], sm, con);
+    if (threadIdx.x == 0) *sm.item = next;
+    __syncthreads();
+    item = *sm.item;
+    __syncthreads();
   }
 }
 

@@ -306,6 +306,12 @@ struct Piece {
 
 void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
   hipStream_t st = c->stream;
+  if (w.size() == 1) {  // one piece fills the chip by itself: the plain per-chunk launches
+    const Piece& pc = w[0];
+    const mra_stack& sk = stacks[pc.stack];
+    run_chunk(c, *pc.rs, pc.p, sk.parts, pc.n0, pc.nc, &sk.out, nullptr);
+    return;
+  }
   const Refset& rs0 = *w[0].rs;
   const int prec = rs0.g.precision, variant = rs0.variant;
   size_t a_floats = 0, rows = 0, part_total = 0;
