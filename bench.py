@@ -20,6 +20,8 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -32,7 +34,10 @@ if ROOT not in sys.path:
 METRIC = "aligned particles/s (L=76,K=100,±3px); FP32 vs BF16-MFMA; p50/p99 latency"
 FP32_MATRIX_PEAK = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 BF16_MATRIX_PEAK = 2500.0  # TFLOP/s, dense
-FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector (published)
+FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
+# reachable without packed FP32 (which this build disables): 256 CUs x 4 SIMDs
+# x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_VALU_PEAK = 78.6
 HBM_PEAK = 8000.0          # GB/s
 # HBM bytes per launch of the FP32 correlation kernel on this workload, from
 # FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) counters calibrated on a 1 GiB
@@ -62,9 +67,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--forms", default="fp32,bf16,fp16")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-h2d", action="store_true", help="skip the pinned-host-memory pass")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reads and writes MIB MiB), "
                          "a reference for hardware traffic counters")
@@ -115,17 +121,47 @@ def main() -> int:
         torch.cuda.synchronize()
         ctx.profile(True)
         torch.cuda.synchronize()
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
+        marks[0].record(ctx.stream)
         for k in range(args.steps):
             step()
+            marks[k + 1].record(ctx.stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        per_step = [marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)]
         kern = {name: ctx.profile_read(name) for name in ("polar", "corr", "merge", "rescore", "averages")}
         ctx.profile(False)
         ms = dt * 1000.0 / args.steps
-        log(f"{form}: {ms:.2f} ms/step, {N / (ms / 1000):.4g} particles/s; kernels "
-            + ", ".join(f"{k} {v[0] / args.steps:.2f} ms" for k, v in kern.items() if v[1]))
-        results[form] = dict(ms=ms, value=N / (ms / 1000.0), kern=kern, out=out.to_numpy())
+        log(f"{form}: {ms:.2f} ms/step (median {statistics.median(per_step):.2f}), {N / (ms / 1000):.4g} "
+            "particles/s; kernels " + ", ".join(f"{k} {v[0] / args.steps:.2f} ms" for k, v in kern.items() if v[1]))
+        results[form] = dict(ms=ms, median_ms=statistics.median(per_step), value=N / (ms / 1000.0), kern=kern,
+                             out=out.to_numpy())
+
+    # ---- the same pass with the particles in pinned host memory (H2D copy inside the timing) ----
+    h2d = None
+    if "fp32" in forms and not args.no_h2d:
+        host = parts.cpu().pin_memory()
+        i = forms.index("fp32")
+        out = mra.AlignResult.empty(N, dev)
+        avg = refs.clone()
+        staged = torch.empty_like(parts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        staged.copy_(host, non_blocking=True)
+        t1e = torch.cuda.Event(enable_timing=True)
+        t0e = torch.cuda.Event(enable_timing=True)
+        t0e.record(ctx.stream)
+        ctx.align(i, staged, out=out)
+        ctx.update_averages(i, staged, out, avg)
+        t1e.record(ctx.stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h2d = dict(value=round(N / dt, 1), unit="particles/s", ms=round(dt * 1000, 3),
+                   copy_gb=round(parts.numel() * 4 / 1e9, 3),
+                   note="fp32 form; particles copied from pinned host memory before the pass (not overlapped)")
+        log(f"fp32 with H2D: {dt * 1000:.1f} ms, {N / dt:.4g} particles/s")
+        del host, staged
 
     # ---- roofline of the dominant kernel (fused correlation, FP32 form) ----
     head = "fp32" if "fp32" in results else forms[0]
@@ -133,8 +169,11 @@ def main() -> int:
     corr_flops = corr_flops_per_row_ref(R) * N * S * K * args.steps
     achieved = corr_flops / (corr_ms / 1000.0) / 1e12
     peak = FP32_MATRIX_PEAK if head == "fp32" else BF16_MATRIX_PEAK
+    R4 = (R + 3) // 4
+    padded = corr_flops * (4 * R4) / R
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4),
+                    frac_padded=round(padded / (corr_ms / 1000.0) / 1e12 / peak, 4),
                     traffic=CORR_FP32_TRAFFIC_BYTES if head == "fp32" else None,
                     traffic_unit="bytes per launch (HBM, counter-measured)",
                     kernel="k_corr", launches_per_step=corr_n // args.steps,
@@ -150,13 +189,32 @@ def main() -> int:
         alu = ifft_flops_per_row_ref() * N * S * K * args.steps / (cms / 1000.0) / 1e12
         mf = corr_flops_per_row_ref(R) * N * S * K * args.steps / (cms / 1000.0) / 1e12
         extra[form] = dict(value=round(r["value"], 1), ms_per_step=round(r["ms"], 3),
+                           median_ms_per_step=round(r["median_ms"], 3),
                            speedup_vs_fp32=round(results[head]["ms"] / r["ms"], 3) if head == "fp32" else None,
                            corr_avg_launch_ms=round(cms / cn, 4),
                            corr_matrix_tflops=round(mf, 2), corr_matrix_frac=round(mf / BF16_MATRIX_PEAK, 4),
-                           corr_ifft_valu_tflops=round(alu, 2), corr_ifft_valu_frac=round(alu / FP32_VECTOR_PEAK, 4))
+                           corr_ifft_valu_tflops=round(alu, 2), corr_ifft_valu_frac=round(alu / FP32_VALU_PEAK, 4))
 
     kernels = {form: {k: round(v[0] / args.steps, 3) for k, v in r["kern"].items() if v[1]}
                for form, r in results.items()}
+
+    # ---- the other kernels against their own rooflines (head form) ----
+    def gbps(nbytes, key):
+        t, n = results[head]["kern"][key]
+        return nbytes * args.steps / (t / 1000.0) / 1e9 if n else float("nan")
+    polar_bytes = N * L * L * 4 + N * S * 1024 * R        # images read + ring spectra written
+    avg_bytes = N * L * L * 4 + 2 * K * L * L * 4         # images read + averages read and written
+    ifft = ifft_flops_per_row_ref() * N * S * K * args.steps / (corr_ms / 1000.0) / 1e12
+    rooflines = {
+        "k_polar_fft": dict(bound="hbm", achieved=round(gbps(polar_bytes, "polar"), 1), peak=HBM_PEAK,
+                            unit="GB/s", frac=round(gbps(polar_bytes, "polar") / HBM_PEAK, 4),
+                            algorithmic_bytes_per_step=polar_bytes),
+        "k_avg": dict(bound="hbm", achieved=round(gbps(avg_bytes, "averages"), 1), peak=HBM_PEAK, unit="GB/s",
+                      frac=round(gbps(avg_bytes, "averages") / HBM_PEAK, 4), algorithmic_bytes_per_step=avg_bytes),
+        "k_corr_ifft": dict(bound="alu", achieved=round(ifft, 2), peak=FP32_VALU_PEAK, unit="TFLOP/s",
+                            frac=round(ifft / FP32_VALU_PEAK, 4), flops_per_row_ref=ifft_flops_per_row_ref(),
+                            note="inverse FFT share of the fused correlation kernel, same launches"),
+    }
 
     # ---- CPU baseline: the FP64 oracle on a sample of the same stack ----
     cpu = None
@@ -180,11 +238,19 @@ def main() -> int:
             threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
         except Exception:
             threads = len(os.sched_getaffinity(0))
+        cpu_model = platform.processor() or "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         cpu = dict(value=round(ns / max(t_all - t_prep, 1e-9), 3), unit="particles/s",
                    cores=int(threads), kind="oracle",
                    sample=f"first {ns} particles of the same stack, FP64 direct ring sums "
                           f"({t_all:.1f} s incl. {t_prep:.1f} s reference preparation, which is excluded "
-                          f"like mra_load_refs on the GPU); host cpus {len(os.sched_getaffinity(0))}")
+                          f"like mra_load_refs on the GPU)",
+                   host=dict(cpu_model=cpu_model, affinity_cpus=len(os.sched_getaffinity(0)),
+                             blas_threads=int(threads)))
         parity = {}
         for form, r in results.items():
             got = {k: v[:ns] for k, v in r["out"].items()}
@@ -217,7 +283,10 @@ def main() -> int:
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "median_ms_per_step": round(results[head]["median_ms"], 3),
+        "rooflines_other_kernels": rooflines,
         "kernels_ms_per_step": kernels,
+        "with_h2d": h2d,
     }
     line.update(extra)
     if parity is not None:

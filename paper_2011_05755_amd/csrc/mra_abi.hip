@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mra.h"
+#include "mra.h"
 #include "mra_common.h"
 
 using namespace mra;
