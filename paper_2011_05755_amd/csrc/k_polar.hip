@@ -69,17 +69,27 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
   const int q0 = row0 >> 3;
   const int ngrp = ((row0 + a.S - 1) >> 3) - q0 + 1;
 
-  for (int ring = w; ring < a.R; ring += 8) {
-    int off[32];
-    float fx[32], fy[32];
+  // (ring, row group) items in contiguous blocks per wave: balanced, and
+  // the stencils are reloaded only when a wave's ring changes
+  const int n_items = a.R * ngrp;
+  const int per_wave = (n_items + 7) / 8;
+  const int it0 = w * per_wave, it1 = min(n_items, it0 + per_wave);
+  int cur = -1;
+  int off[32];
+  float fx[32], fy[32];
+  for (int item = it0; item < it1; ++item) {
+    const int ring = item / ngrp, grp = item - ring * ngrp;
+    if (ring != cur) {
+      cur = ring;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      const Stencil s = a.stencil[ring * kNphi + 16 * (i >> 1) + 2 * l + (i & 1)];
-      off[i] = base + s.dy * a.Lp + s.dx;
-      fx[i] = s.fx;
-      fy[i] = s.fy;
+      for (int i = 0; i < 32; ++i) {
+        const Stencil s = a.stencil[ring * kNphi + 16 * (i >> 1) + 2 * l + (i & 1)];
+        off[i] = base + s.dy * a.Lp + s.dx;
+        fx[i] = s.fx;
+        fy[i] = s.fy;
+      }
     }
-    for (int grp = 0; grp < ngrp; ++grp) {
+    {
       const int row = (q0 + grp) * 8 + rl;
       const int s = row - row0;
       const bool valid = s >= 0 && s < a.S;
@@ -119,11 +129,14 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
 
       if (MODE == 0) {
         // stage [slot][p*8 + row] in this wave's scratch, then write whole
-        // 64-byte (slot, ring) segments of the tile with 16-byte stores
+        // 64-byte (slot, ring) segments of the tile with 16-byte stores.
+        // The four 16-byte chunks of a slot are XOR-swizzled by slot & 3, so
+        // the eight lanes l that write at once hit distinct banks.
         fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
-                   stage[slot * 16 + rl] = re - im;
-                   stage[slot * 16 + 8 + rl] = re + im;
+                   const int sw = (slot & 3) << 2;
+                   stage[slot * 16 + (rl ^ sw)] = re - im;
+                   stage[slot * 16 + ((8 + rl) ^ sw)] = re + im;
                  });
         wave_sync();
         const int tile = q0 + grp;
@@ -137,7 +150,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
 #pragma unroll
         for (int it = 0; it < kSlots / 16; ++it) {
           const int slot = it * 16 + (ln >> 2);
-          const float4 val = *reinterpret_cast<const float4*>(stage + slot * 16 + part * 4);
+          const float4 val = *reinterpret_cast<const float4*>(stage + slot * 16 + ((part ^ (slot & 3)) << 2));
           float* o = dst + slot * slot_stride + part * 4;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;

@@ -138,36 +138,45 @@ MRA_HD void fwd_cols(int l, int& k1a, int& k1b) {
 // Zb[k2] = Z[k1b + 16 k2]; `w256(f)` returns exp(-2 pi i f / 256).
 // emit(slot, a, b) is called once per frequency slot: slot f in 1..127
 // receives (Re P_f, Im P_f); slot 0 receives (P_0, P_128), both real.
+//
+// Every lane runs the same eight steps (lane 0's special bins are patched
+// in by selects, so a wave never splits); step k2 emits the slots f and
+// 128 - f of one real split:
+//   l != 0:  f = l + 16 k2            from (Za[k2], Zb[7 - k2])
+//   l == 0:  k2 = 1..3: f = 16 k2     from (Za[k2], Za[8 - k2])
+//            k2 = 4..7: f = 16 k2 - 56 from (Zb[k2 - 4], Zb[11 - k2])
+//            k2 = 0: slot 0 = (P_0, P_128) = (Re + Im, Re - Im) of Z_0 and
+//                    slot 64 = conj Z_64 (f = 64 pairs with itself)
 template <class W, class E>
 MRA_HD void fwd_emit(int l, const float2 (&Za)[8], const float2 (&Zb)[8], W w256, E emit) {
-  if (l == 0) {
-    // f = 0 and 128 from Z_0
-    emit(0, Za[0].x + Za[0].y, Za[0].x - Za[0].y);
-    // f = 64 pairs with itself: P_64 = conj(Z_64)
-    emit(64, Za[4].x, -Za[4].y);
+  const bool z = l == 0;
 #pragma unroll
-    for (int k2 = 1; k2 < 4; ++k2) {          // f = 16 k2, g = 16 (8 - k2)
-      float2 pf, pg;
-      real_split(Za[k2], Za[8 - k2], w256(16 * k2), pf, pg);
-      emit(16 * k2, pf.x, pf.y);
-      emit(128 - 16 * k2, pg.x, pg.y);
+  for (int k2 = 0; k2 < 8; ++k2) {
+    float2 x, y;
+    int f;
+    if (k2 == 0) {
+      x = Za[0];
+      y = Zb[7];
+      f = l;
+    } else if (k2 < 4) {
+      x = Za[k2];
+      y = z ? Za[8 - k2] : Zb[7 - k2];
+      f = z ? 16 * k2 : l + 16 * k2;
+    } else {
+      x = z ? Zb[k2 - 4] : Za[k2];
+      y = z ? Zb[11 - k2] : Zb[7 - k2];
+      f = z ? 16 * k2 - 56 : l + 16 * k2;
     }
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {          // f = 8 + 16 k2, g = 8 + 16 (7 - k2)
-      float2 pf, pg;
-      real_split(Zb[k2], Zb[7 - k2], w256(8 + 16 * k2), pf, pg);
-      emit(8 + 16 * k2, pf.x, pf.y);
-      emit(120 - 16 * k2, pg.x, pg.y);
+    float2 pf, pg;
+    real_split(x, y, w256(f), pf, pg);
+    int g = 128 - f;
+    if (k2 == 0) {
+      pf = z ? make_float2(Za[0].x + Za[0].y, Za[0].x - Za[0].y) : pf;
+      pg = z ? make_float2(Za[4].x, -Za[4].y) : pg;
+      g = z ? 64 : g;
     }
-  } else {
-#pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {          // f = l + 16 k2, g = (16 - l) + 16 (7 - k2)
-      float2 pf, pg;
-      const int f = l + 16 * k2;
-      real_split(Za[k2], Zb[7 - k2], w256(f), pf, pg);
-      emit(f, pf.x, pf.y);
-      emit(128 - f, pg.x, pg.y);
-    }
+    emit(f, pf.x, pf.y);
+    emit(g, pg.x, pg.y);
   }
 }
 
