@@ -92,7 +92,11 @@ typedef struct mra_result {
   int32_t* psi;
   int32_t* mirror;
   float* cc;
-  float* cc2;          /* optional: best CC over every other candidate      */
+  float* cc2;          /* optional: best CC over every other candidate (all
+                          shifts, mirrors, references and angles but the
+                          winner; equal to cc on a tie), from a second
+                          contraction pass with the winner left out, in the
+                          form's contraction precision.  NULL skips the pass. */
   int32_t* flat_index; /* optional: iota of the winner                      */
 } mra_result;
 
@@ -189,7 +193,8 @@ int mra_debug_refs(mra_ctx* ctx, int32_t refset_id, float* qhat, double* norm);
 
 /* Kernel timing for measurement.  mra_profile(ctx, 1) clears and starts
  * recording a HIP event pair around every launch of the named kernel groups
- * ("polar", "corr", "merge", "rescore", "averages") on the context's stream;
+ * ("polar", "corr", "merge", "rescore", "maxabs", "averages", and "corr2" for
+ * the runner-up pass of cc2) on the context's stream;
  * mra_profile(ctx, 0) stops.  mra_profile_read synchronises the stream and
  * returns the summed device time and the launch count of one group. */
 int mra_profile(mra_ctx* ctx, int enable);

@@ -317,8 +317,12 @@ __device__ __forceinline__ float fp16_scale(const CorrArgs& a, int r) {
   return ldexpf(1.f, 14 - (int)ceilf(log2f(m)));
 }
 
+// What a tile computes: the per-row arg-max, the full CC table (debug), or
+// the arg-max with one candidate per particle left out (the runner-up pass).
+constexpr int kArgmax = 0, kTable = 1, kRunnerUp = 2;
+
 // One 8-row tile against every reference tile (see the file comment).
-template <int PREC, int NW, class Contract, bool TABLE>
+template <int PREC, int NW, class Contract, int MODE>
 __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const CorrSmem<NW>& sm, Contract& con) {
   const int tid = threadIdx.x, ln = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -359,6 +363,17 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     const float thr = sm.rb_v[row_l];
     float bv = -INFINITY;
     int bi = 0x7fffffff;
+    // the candidate left out of this pass (key m * 256 + angle of this
+    // lane's (row, ref)), or -1
+    int ex = -1;
+    if (MODE == kRunnerUp && row < a.rows && k < a.K) {
+      const int n = row / a.S, s = row - n * a.S;
+      const int e = a.excl[n];
+      if (e >= 0) {
+        const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
+        if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
+      }
+    }
 #pragma unroll 1
     for (int c = 0; c < 16 / NW; ++c) {
       const int n1 = w + NW * c;
@@ -366,7 +381,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[vidx(16 * n1 + k2, P)];
       inv_pass2(x);
-      if constexpr (TABLE) {
+      if constexpr (MODE == kTable) {
         if (row < a.rows && k < a.K) {
           const int n = row / a.S, s = row - n * a.S;
           const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
@@ -384,18 +399,21 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
 #pragma unroll
           for (int n2 = 0; n2 < 16; ++n2) {
             const int ang = n1 + 16 * n2;
-            if (better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
-            if (a.M == 2 && better(x[n2].y, 256 + ang, bv, bi)) { bv = x[n2].y; bi = 256 + ang; }
+            if ((MODE != kRunnerUp || ang != ex) && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+            if (a.M == 2 && (MODE != kRunnerUp || 256 + ang != ex) && better(x[n2].y, 256 + ang, bv, bi)) {
+              bv = x[n2].y;
+              bi = 256 + ang;
+            }
           }
         }
       }
     }
-    if constexpr (!TABLE) {
+    if constexpr (MODE != kTable) {
       sm.cand_v[w * 64 + P] = bv;
       sm.cand_i[w * 64 + P] = bi;
     }
     __syncthreads();
-    if constexpr (!TABLE) {
+    if constexpr (MODE != kTable) {
       // waves reduce the 8 rows: lane = (wave of origin, ref)
       for (int r = w; r < kRowTile; r += NW) {
         const int ww = ln >> 3, ref = ln & 7;
@@ -426,7 +444,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     }
     __syncthreads();
   }
-  if (!TABLE && tid < 8) {
+  if (MODE != kTable && tid < 8) {
     const int r = tile * kRowTile + tid;
     if (r < a.rows) {
       const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, r) * a.b_scale) : 1.f;
@@ -442,13 +460,13 @@ struct ContractFor {
                                     Half16Contract<PREC == kFP32 ? kBF16 : PREC, NW, MAXR, EXACT, RES>>::type type;
 };
 
-template <int PREC, int NW, int MAXR, bool RES, bool EXACT, bool TABLE>
+template <int PREC, int NW, int MAXR, bool RES, bool EXACT, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_corr(CorrArgs a) {
   extern __shared__ float smem[];
   CorrSmem<NW> sm(smem);
   if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(a.cs32, threadIdx.x);
   typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
-  corr_tile<PREC, NW, decltype(con), TABLE>(a, blockIdx.x, sm, con);
+  corr_tile<PREC, NW, decltype(con), MODE>(a, blockIdx.x, sm, con);
 }
 
 // Persistent form over the row tiles of several stacks.  Workgroup g takes
@@ -469,7 +487,7 @@ __global__ __launch_bounds__(NW * 64) void k_corr_batch(CorrBatch b) {
     if (threadIdx.x == 0) next = atomicAdd(b.counter, 1) + (int)gridDim.x;
     int p = 0;
     while (p + 1 < b.n && b.tile_start[p + 1] <= item) ++p;
-    corr_tile<PREC, NW, decltype(con), false>(b.piece[p], item - b.tile_start[p], sm, con);
+    corr_tile<PREC, NW, decltype(con), kArgmax>(b.piece[p], item - b.tile_start[p], sm, con);
     if (threadIdx.x == 0) *sm.item = next;
     __syncthreads();
     item = *sm.item;
@@ -483,12 +501,16 @@ struct Cfg {
   static constexpr bool RES = RES_, EXACT = EXACT_;
 };
 
+template <class C, int MODE>
+inline void launch_mode(const CorrArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, MODE>), dim3(a.n_row_tiles), dim3(C::NW * 64),
+                     CorrSmem<C::NW>::bytes(), st, a);
+}
+
 template <class C>
 inline void launch_one(const CorrArgs& a, bool table, hipStream_t st) {
-  const dim3 grid(a.n_row_tiles), block(C::NW * 64);
-  const size_t lds = CorrSmem<C::NW>::bytes();
-  if (table) hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, true>), grid, block, lds, st, a);
-  else hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, false>), grid, block, lds, st, a);
+  if (table) launch_mode<C, kTable>(a, st);
+  else launch_mode<C, kArgmax>(a, st);
 }
 
 template <class C>
@@ -506,6 +528,12 @@ void corr_dispatch_bf16(int variant, int r4min, int r4max, const CorrArgs* a, bo
                         int grid, hipStream_t st);
 void corr_dispatch_fp16(int variant, int r4min, int r4max, const CorrArgs* a, bool table, const CorrBatch* b,
                         int grid, hipStream_t st);
+
+// The runner-up pass (one instantiation per precision: the generic
+// streamed-operand configuration, any R4 <= 16).
+void corr_runner_up_fp32(const CorrArgs& a, hipStream_t st);
+void corr_runner_up_bf16(const CorrArgs& a, hipStream_t st);
+void corr_runner_up_fp16(const CorrArgs& a, hipStream_t st);
 
 template <class C>
 inline void corr_go(const CorrArgs* a, bool table, const CorrBatch* b, int grid, hipStream_t st) {

@@ -36,6 +36,15 @@ hipError_t launch_corr(int prec, int variant, bool table, const CorrArgs& a, hip
   return hipGetLastError();
 }
 
+hipError_t launch_corr_runner_up(int prec, const CorrArgs& a, hipStream_t st) {
+  if (a.n_row_tiles <= 0) return hipSuccess;
+  if (a.R4 < 1 || a.R4 > 16 || !a.excl) return hipErrorInvalidValue;
+  if (prec == kFP32) corr_runner_up_fp32(a, st);
+  else if (prec == kBF16) corr_runner_up_bf16(a, st);
+  else corr_runner_up_fp16(a, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_corr_batch(int prec, int variant, const CorrBatch& b, int grid, hipStream_t st) {
   if (b.n <= 0 || grid <= 0) return hipSuccess;
   int r4min = 1 << 30, r4max = 0;
@@ -59,6 +68,11 @@ __device__ __forceinline__ void merge_particle(const MergeArgs& a, int n) {
     if (better(v, i, best, bi)) { best = v; bi = i; }
   }
   const int64_t o = a.out_off + n;
+  if (a.runner_up) {  // second pass: the best over every candidate but the winner
+    a.cc2[o] = bi == 0x7fffffff ? NAN : best;
+    return;
+  }
+  if (a.win) a.win[n] = bi == 0x7fffffff ? -1 : bi;
   if (bi == 0x7fffffff) {  // no ordered candidate (NaN input): report an invalid winner
     a.ref[o] = -1;
     a.mirror[o] = 0;

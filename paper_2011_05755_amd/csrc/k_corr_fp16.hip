@@ -11,4 +11,8 @@ void corr_dispatch_fp16(int variant, int r4min, int r4max, const CorrArgs* a, bo
   else corr_dispatch_16<kFP16, false>(r4min, r4max, a, table, b, grid, st);
 }
 
+void corr_runner_up_fp16(const CorrArgs& a, hipStream_t st) {
+  launch_mode<Cfg<kFP16, 8, 16, false, false>, kRunnerUp>(a, st);
+}
+
 }  // namespace mra

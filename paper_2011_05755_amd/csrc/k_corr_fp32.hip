@@ -26,4 +26,8 @@ void corr_dispatch_fp32(int variant, int r4min, int r4max, const CorrArgs* a, bo
   return go(Cfg<kFP32, 8, 16, false, false>{});
 }
 
+void corr_runner_up_fp32(const CorrArgs& a, hipStream_t st) {
+  launch_mode<Cfg<kFP32, 8, 16, false, false>, kRunnerUp>(a, st);
+}
+
 }  // namespace mra

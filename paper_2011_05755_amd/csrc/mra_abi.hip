@@ -259,6 +259,8 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ma.ref = out->ref; ma.shift_x = out->shift_x; ma.shift_y = out->shift_y;
   ma.psi = out->psi; ma.mirror = out->mirror; ma.flat = out->flat_index;
   ma.cc = out->cc; ma.cc2 = out->cc2;
+  int32_t* win = out->cc2 ? (int32_t*)ws_get(c, "win", (size_t)nc * sizeof(int32_t)) : nullptr;
+  ma.win = win;
   timed(c, "merge", [&] { hip_check(c, launch_merge(ma, st), "merge"); });
 
   if (rs.g.precision != kFP32) {
@@ -274,6 +276,17 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
     ra.psi = out->psi; ra.mirror = out->mirror;
     ra.cc = out->cc;
     timed(c, "rescore", [&] { hip_check(c, launch_rescore(ra, st), "rescore"); });
+  }
+
+  if (out->cc2) {
+    // runner-up: the same contraction with each particle's winner left out;
+    // the best that remains is the best over every other candidate
+    ca.excl = win;
+    timed(c, "corr2", [&] { hip_check(c, launch_corr_runner_up(rs.g.precision, ca, st), "corr2"); });
+    MergeArgs m2 = ma;
+    m2.win = nullptr;
+    m2.runner_up = 1;
+    timed(c, "merge", [&] { hip_check(c, launch_merge(m2, st), "merge"); });
   }
 }
 
@@ -413,6 +426,12 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
     if (s.N <= 0) continue;
     const Refset& rs = get_refset(c, s.refset_id);
     const Plan& p = plans[i];
+    if (s.out.cc2) {  // runner-up requested: the per-chunk path, which runs the second pass
+      const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
+      for (int64_t n0 = 0; n0 < s.N; n0 += step)
+        run_chunk(c, rs, p, s.parts, n0, (int)std::min<int64_t>(step, s.N - n0), &s.out, nullptr);
+      continue;
+    }
     const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
     const int64_t cap_n = rs.chunk > 0 ? rs.chunk : std::max<int64_t>(1, (int64_t)(budget / per));
     for (int64_t n0 = 0; n0 < s.N;) {

@@ -56,6 +56,7 @@ struct CorrArgs {
   float* row_cc;         // [rows] best CC of the row
   int* row_idx;          // [rows] flat index of the row's best
   float* table;          // debug: [n][K][M][S][256], else null
+  const int* excl;       // per particle of the chunk: flat index left out of the arg-max, or null
 };
 
 // Batched correlation: pieces of several stacks in one persistent launch.
@@ -74,6 +75,8 @@ struct MergeArgs {
   int64_t out_off;
   int32_t *ref, *shift_x, *shift_y, *psi, *mirror, *flat;
   float *cc, *cc2;
+  int32_t* win;          // chunk-local copy of each winner's flat index, or null
+  int runner_up;         // 1: rows hold the best without the winner; write only cc2
 };
 
 struct RescoreArgs {
@@ -109,6 +112,7 @@ struct RescoreBatch {
 hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st);
 size_t polar_lds_bytes(int Lp);
 hipError_t launch_corr(int prec, int variant, bool table, const CorrArgs& a, hipStream_t st);
+hipError_t launch_corr_runner_up(int prec, const CorrArgs& a, hipStream_t st);
 hipError_t launch_corr_batch(int prec, int variant, const CorrBatch& b, int grid, hipStream_t st);
 bool corr_variant_ok(int prec, int variant, int R4);
 int corr_default_variant(int prec, int R4);

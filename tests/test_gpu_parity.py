@@ -124,6 +124,33 @@ def test_align_fp32_small_shapes_and_ragged_sizes(ctx, N):
     log(f"  max rel CC err {err:.2e}")
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3), ("fp16", 2e-3)])
+def test_runner_up_cc2(ctx, precision, tol):
+    """cc2 (best over every candidate but the winner, from the second pass)
+    against the oracle's, relative to |cc|; the other outputs are those of a
+    run without cc2; batch and single agree."""
+    from paper_2011_05755_amd import mra
+    log(f"runner-up cc2 {precision}")
+    L, K, T, N = 64, 10, 2, 23
+    refs, parts, _ = make_case(L, K, T, N, 0.1, 70)
+    ctx.load_refs(40, refs, r_min=1, r_max=30, shift_max=T, precision=precision)
+    res = ctx.align(40, parts, with_cc2=True).to_numpy()
+    want = oracle.align(parts.cpu().numpy(), refs.cpu().numpy(), geom(L, 30, T))
+    rel = np.abs(res["cc2"] - want["cc2"]) / np.abs(want["cc"])
+    assert rel.max() <= tol, f"max rel cc2 err {rel.max():.3g}"
+    if precision == "fp32":
+        assert np.all(res["cc2"] <= res["cc"])
+    plain = ctx.align(40, parts).to_numpy()
+    for key in plain:
+        np.testing.assert_array_equal(res[key], plain[key])
+    out = mra.AlignResult.empty(N, DEV, with_cc2=True)
+    ctx.align_batch([(40, parts, -1, out)])
+    got = out.to_numpy()
+    for key in res:
+        np.testing.assert_array_equal(got[key], res[key])
+    log(f"  max rel cc2 err {rel.max():.2e}")
+
+
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 def test_align_mixed_precision_with_fp32_rescore(ctx, precision):
     log(f"align {precision} L=64 K=10 T=2 N=48")
