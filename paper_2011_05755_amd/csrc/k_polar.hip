@@ -60,8 +60,6 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
   const int l = ln >> 3, rl = ln & 7;
   float2* my = scr + w * 64 * 17;
   float* stage = reinterpret_cast<float*>(my);  // [128 slots][16] after the transpose
-  int k1a, k1b;
-  fwd_cols(l, k1a, k1b);
   const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
   // lane rl handles row (q0 + grp) * 8 + rl: groups are aligned to the
   // correlation kernel's 8-row tiles
@@ -90,7 +88,15 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       }
     }
     {
-      const int row = (q0 + grp) * 8 + rl;
+      // The lane indices are made opaque here, so that the LDS and twiddle
+      // addresses derived from them are recomputed in every item instead of
+      // being hoisted out of the loop, where they do not fit in registers
+      // next to the stencils and would be spilled to scratch.
+      int lx = l, rx = rl, lnx = ln;
+      asm volatile("" : "+v"(lx), "+v"(rx), "+v"(lnx));
+      int k1a, k1b;
+      fwd_cols(lx, k1a, k1b);
+      const int row = (q0 + grp) * 8 + rx;
       const int s = row - row0;
       const bool valid = s >= 0 && s < a.S;
       const int sc = s < 0 ? 0 : (s < a.S ? s : a.S - 1);
@@ -103,7 +109,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         if (valid) {
           float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * kNphi;
 #pragma unroll
-          for (int i = 0; i < 32; ++i) o[16 * (i >> 1) + 2 * l + (i & 1)] = v[i];
+          for (int i = 0; i < 32; ++i) o[16 * (i >> 1) + 2 * lx + (i & 1)] = v[i];
         }
         continue;
       }
@@ -113,15 +119,15 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
       dft16<-1>(z);
 #pragma unroll
-      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((l * k1) & 127)]);
+      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((lx * k1) & 127)]);
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) my[(rl * 8 + l) * 17 + k1] = z[k1];
+      for (int k1 = 0; k1 < 16; ++k1) my[(rx * 8 + lx) * 17 + k1] = z[k1];
       wave_sync();
       float2 Za[8], Zb[8];
 #pragma unroll
       for (int n2 = 0; n2 < 8; ++n2) {
-        Za[n2] = my[(rl * 8 + n2) * 17 + k1a];
-        Zb[n2] = my[(rl * 8 + n2) * 17 + k1b];
+        Za[n2] = my[(rx * 8 + n2) * 17 + k1a];
+        Zb[n2] = my[(rx * 8 + n2) * 17 + k1b];
       }
       wave_sync();
       dft8<-1>(Za);
@@ -132,11 +138,11 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         // 64-byte (slot, ring) segments of the tile with 16-byte stores.
         // The four 16-byte chunks of a slot are XOR-swizzled by slot & 3, so
         // the eight lanes l that write at once hit distinct banks.
-        fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
+        fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
                    const int sw = (slot & 3) << 2;
-                   stage[slot * 16 + (rl ^ sw)] = re - im;
-                   stage[slot * 16 + ((8 + rl) ^ sw)] = re + im;
+                   stage[slot * 16 + (rx ^ sw)] = re - im;
+                   stage[slot * 16 + ((8 + rx) ^ sw)] = re + im;
                  });
         wave_sync();
         const int tile = q0 + grp;
@@ -144,12 +150,12 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         const int last = row0 + a.S - tile * 8;       // first row after the particle
         float* dst = a.out + (size_t)tile * kSlots * a.R4 * 64 + ring * 16;
         const size_t slot_stride = (size_t)a.R4 * 64;
-        const int part = ln & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
+        const int part = lnx & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
         const int r0 = (part & 1) * 4;
         const bool full = r0 >= first && r0 + 4 <= last;
 #pragma unroll
         for (int it = 0; it < kSlots / 16; ++it) {
-          const int slot = it * 16 + (ln >> 2);
+          const int slot = it * 16 + (lnx >> 2);
           const float4 val = *reinterpret_cast<const float4*>(stage + slot * 16 + ((part ^ (slot & 3)) << 2));
           float* o = dst + slot * slot_stride + part * 4;
           if (full) {
@@ -164,7 +170,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         wave_sync();
       } else {  // MODE 2: plain spectra
         float* o = a.out + (((size_t)n * a.S + (valid ? s : 0)) * a.R + ring) * 129 * 2;
-        fwd_emit(l, Za, Zb, [&](int f) { return tw[f & 255]; },
+        fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
                  [&](int slot, float re, float im) {
                    if (!valid) return;
                    if (slot == 0) {
