@@ -1,14 +1,17 @@
 // Shift + polar resampling and per-ring FFT of particle images (Algorithm 1:
 // "convert x_i to polar coordinates with given shift and apply FFT"), the
-// FP32 re-score of a winning candidate, and a max-|x| reduction.
+// FP32 re-score of a winning candidate, and the per-particle max |pixel|.
 //
-// One workgroup per particle.  The image is staged once in LDS with a zero
-// border (coalesced HBM read), then every wave takes one ring at a time for
-// eight shifts at once: lane (l, row) holds the 32 samples p[16 n1 + 2l + e]
-// of shift `row`, whose bilinear stencils stay in registers for all shifts
-// (integer shifts move the stencil by whole pixels).  The 256-point real FFT
-// runs as a 16 x 8 complex FFT across the eight lanes l of a shift with one
-// transpose through a per-wave LDS scratch.
+// One 4-wave workgroup per particle (about 50 KB of LDS at L = 76, so three
+// workgroups share a CU).  The image is staged once in LDS with a zero
+// border (coalesced HBM read); the (ring, 8-row group) items of the
+// particle are split between the waves.  In an item, lane (l, row) takes the
+// 32 samples p[16 n1 + 2l + e] of shift `row` (integer shifts move the
+// bilinear stencil by whole pixels, so all shifts share one stencil table,
+// read from the cache).  The 256-point real FFT runs as a 16 x 8 complex FFT
+// across the eight lanes l of a shift, with a transpose through a per-wave
+// LDS scratch, and the spectra are staged there again so that the operand is
+// written in whole 64-byte segments.
 #include "mra_common.h"
 #include "mra_fft.h"
 
@@ -51,15 +54,15 @@ template <int MODE>
 __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float* smem) {
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
-  float2* tw = scr + 8 * 64 * 17;  // exp(-2 pi i e / 256), e = 0..255
+  float2* tw = scr + kPolarWaves * 64 * 9;  // exp(-2 pi i e / 256), e = 0..255
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
   if (threadIdx.x < kNphi) tw[threadIdx.x] = w256f(a.cs32, threadIdx.x);
   __syncthreads();
 
   const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int l = ln >> 3, rl = ln & 7;
-  float2* my = scr + w * 64 * 17;
-  float* stage = reinterpret_cast<float*>(my);  // [128 slots][16] after the transpose
+  float2* my = scr + w * 64 * 9;                // per-wave scratch: 64 lanes x 9 float2
+  float* stage = reinterpret_cast<float*>(my);  // [64 slots][16] in each staging round
   const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
   // lane rl handles row (q0 + grp) * 8 + rl: groups are aligned to the
   // correlation kernel's 8-row tiles
@@ -67,97 +70,131 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
   const int q0 = row0 >> 3;
   const int ngrp = ((row0 + a.S - 1) >> 3) - q0 + 1;
 
-  // (ring, row group) items in contiguous blocks per wave: balanced, and
-  // the stencils are reloaded only when a wave's ring changes
+  // (ring, row group) items in contiguous blocks per wave (balanced)
   const int n_items = a.R * ngrp;
-  const int per_wave = (n_items + 7) / 8;
+  const int per_wave = (n_items + kPolarWaves - 1) / kPolarWaves;
   const int it0 = w * per_wave, it1 = min(n_items, it0 + per_wave);
-  int cur = -1;
-  int off[32];
-  float fx[32], fy[32];
   for (int item = it0; item < it1; ++item) {
     const int ring = item / ngrp, grp = item - ring * ngrp;
-    if (ring != cur) {
-      cur = ring;
+    // The lane indices are made opaque here, so that the LDS and twiddle
+    // addresses derived from them are recomputed in every item instead of
+    // being hoisted out of the loop and kept in registers.
+    int lx = l, rx = rl, lnx = ln;
+    asm volatile("" : "+v"(lx), "+v"(rx), "+v"(lnx));
+    int k1a, k1b;
+    fwd_cols(lx, k1a, k1b);
+    const int row = (q0 + grp) * 8 + rx;
+    const int s = row - row0;
+    const bool valid = s >= 0 && s < a.S;
+    const int sc = s < 0 ? 0 : (s < a.S ? s : a.S - 1);
+    const int soff = (sc / a.S1 - a.T) * a.Lp + (sc % a.S1 - a.T);
+
+    // 32 bilinear samples p[16 n1 + 2 l + e] of this lane's shift; the
+    // stencils (shared by all shifts) are read from the cache in two
+    // batches of 16 rather than pinned in registers
+    const Stencil* sp = a.stencil + ring * kNphi + 2 * lx;
+    float v[32];
 #pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        const Stencil s = a.stencil[ring * kNphi + 16 * (i >> 1) + 2 * l + (i & 1)];
-        off[i] = base + s.dy * a.Lp + s.dx;
-        fx[i] = s.fx;
-        fy[i] = s.fy;
+    for (int h = 0; h < 2; ++h) {
+      Stencil st[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int i = 16 * h + j;
+        st[j] = sp[16 * (i >> 1) + (i & 1)];
       }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        v[16 * h + j] = bilin(img, base + __mul24(st[j].dy, a.Lp) + st[j].dx + soff, a.Lp, st[j].fx, st[j].fy);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    {
-      // The lane indices are made opaque here, so that the LDS and twiddle
-      // addresses derived from them are recomputed in every item instead of
-      // being hoisted out of the loop, where they do not fit in registers
-      // next to the stencils and would be spilled to scratch.
-      int lx = l, rx = rl, lnx = ln;
-      asm volatile("" : "+v"(lx), "+v"(rx), "+v"(lnx));
-      int k1a, k1b;
-      fwd_cols(lx, k1a, k1b);
-      const int row = (q0 + grp) * 8 + rx;
-      const int s = row - row0;
-      const bool valid = s >= 0 && s < a.S;
-      const int sc = s < 0 ? 0 : (s < a.S ? s : a.S - 1);
-      const int soff = (sc / a.S1 - a.T) * a.Lp + (sc % a.S1 - a.T);
-      float v[32];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) v[i] = bilin(img, off[i] + soff, a.Lp, fx[i], fy[i]);
 
-      if (MODE == 1) {
-        if (valid) {
-          float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * kNphi;
+    if (MODE == 1) {
+      if (valid) {
+        float* o = a.out + (((size_t)n * a.S + s) * a.R + ring) * kNphi;
 #pragma unroll
-          for (int i = 0; i < 32; ++i) o[16 * (i >> 1) + 2 * lx + (i & 1)] = v[i];
-        }
-        continue;
+        for (int i = 0; i < 32; ++i) o[16 * (i >> 1) + 2 * lx + (i & 1)] = v[i];
       }
+      continue;
+    }
 
-      float2 z[16];
+    float2 z[16];
 #pragma unroll
-      for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
-      dft16<-1>(z);
+    for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
+    dft16<-1>(z);
 #pragma unroll
-      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((lx * k1) & 127)]);
+    for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((lx * k1) & 127)]);
+    // transpose through the scratch in two halves: lane l's first column
+    // k1a lies in 0..7, its second k1b in 8..15.  Entries are ordered
+    // (l, shift) with the shift fastest, which spreads a wave's accesses
+    // over the banks better than (shift, l).
+    float2 Za[8], Zb[8];
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) my[(rx * 8 + lx) * 17 + k1] = z[k1];
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int k1 = 0; k1 < 8; ++k1) my[(lx * 8 + rx) * 9 + k1] = z[8 * h + k1];
       wave_sync();
-      float2 Za[8], Zb[8];
 #pragma unroll
       for (int n2 = 0; n2 < 8; ++n2) {
-        Za[n2] = my[(rx * 8 + n2) * 17 + k1a];
-        Zb[n2] = my[(rx * 8 + n2) * 17 + k1b];
+        if (h == 0) Za[n2] = my[(n2 * 8 + rx) * 9 + k1a];
+        else Zb[n2] = my[(n2 * 8 + rx) * 9 + k1b - 8];
       }
       wave_sync();
-      dft8<-1>(Za);
-      dft8<-1>(Zb);
+    }
+    dft8<-1>(Za);
+    dft8<-1>(Zb);
 
-      if (MODE == 0) {
-        // stage [slot][p*8 + row] in this wave's scratch, then write whole
-        // 64-byte (slot, ring) segments of the tile with 16-byte stores.
-        // The four 16-byte chunks of a slot are XOR-swizzled by slot & 3, so
-        // the eight lanes l that write at once hit distinct banks.
-        fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
-                 [&](int slot, float re, float im) {
-                   const int sw = (slot & 3) << 2;
-                   stage[slot * 16 + (rx ^ sw)] = re - im;
-                   stage[slot * 16 + ((8 + rx) ^ sw)] = re + im;
-                 });
-        wave_sync();
-        const int tile = q0 + grp;
-        const int first = row0 - tile * 8;            // rows of this tile before the particle
-        const int last = row0 + a.S - tile * 8;       // first row after the particle
-        float* dst = a.out + (size_t)tile * kSlots * a.R4 * 64 + ring * 16;
-        const size_t slot_stride = (size_t)a.R4 * 64;
-        const int part = lnx & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
-        const int r0 = (part & 1) * 4;
-        const bool full = r0 >= first && r0 + 4 <= last;
+    if (MODE == 0) {
+      // Every real split yields one slot below 64 and one above (128 - f, or
+      // lane 0's 0 and 64): keep both, then stage [slot][p*8 + row] for the
+      // 64 low slots and then the 64 high ones, and write whole 64-byte
+      // (slot, ring) segments of the tile with 16-byte stores.  The four
+      // 16-byte chunks of a slot are XOR-swizzled by slot & 3, so the eight
+      // lanes l that write at once hit distinct banks.
+      int lo_s[8], hi_s[8];
+      float lo_a[8], lo_b[8], hi_a[8], hi_b[8];
+      int e = 0, s0 = 0;
+      float a0 = 0.f, b0 = 0.f;
+      fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
+               [&](int slot, float re, float im) {
+                 const int k = e >> 1;
+                 if ((e++ & 1) == 0) {
+                   s0 = slot; a0 = re - im; b0 = re + im;
+                 } else {
+                   const bool first_low = s0 < slot;
+                   lo_s[k] = first_low ? s0 : slot;
+                   hi_s[k] = first_low ? slot : s0;
+                   lo_a[k] = first_low ? a0 : re - im;
+                   lo_b[k] = first_low ? b0 : re + im;
+                   hi_a[k] = first_low ? re - im : a0;
+                   hi_b[k] = first_low ? re + im : b0;
+                 }
+               });
+      const int tile = q0 + grp;
+      const int first = row0 - tile * 8;            // rows of this tile before the particle
+      const int last = row0 + a.S - tile * 8;       // first row after the particle
+      float* dst = a.out + (size_t)tile * kSlots * a.R4 * 64 + ring * 16;
+      const size_t slot_stride = (size_t)a.R4 * 64;
+      const int part = lnx & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
+      const int r0 = (part & 1) * 4;
+      const bool full = r0 >= first && r0 + 4 <= last;
+      // the lane's segment of slot 16 * it + (lane / 4) + 64 * h: one vector
+      // multiply per item, the rest is a uniform offset
+      float* const lane_dst = dst + (size_t)__mul24(lnx >> 2, (int)slot_stride) + part * 4;
 #pragma unroll
-        for (int it = 0; it < kSlots / 16; ++it) {
-          const int slot = it * 16 + (lnx >> 2);
-          const float4 val = *reinterpret_cast<const float4*>(stage + slot * 16 + ((part ^ (slot & 3)) << 2));
-          float* o = dst + slot * slot_stride + part * 4;
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int sl = h ? hi_s[k] - 64 : lo_s[k];
+          const int sw = (sl & 3) << 2;
+          stage[sl * 16 + (rx ^ sw)] = h ? hi_a[k] : lo_a[k];
+          stage[sl * 16 + ((8 + rx) ^ sw)] = h ? hi_b[k] : lo_b[k];
+        }
+        wave_sync();
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int sl = it * 16 + (lnx >> 2);
+          const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
+          float* o = lane_dst + (size_t)(64 * h + 16 * it) * slot_stride;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;
           } else {
@@ -168,20 +205,20 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
           }
         }
         wave_sync();
-      } else {  // MODE 2: plain spectra
-        float* o = a.out + (((size_t)n * a.S + (valid ? s : 0)) * a.R + ring) * 129 * 2;
-        fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
-                 [&](int slot, float re, float im) {
-                   if (!valid) return;
-                   if (slot == 0) {
-                     o[0] = re; o[1] = 0.f;
-                     o[256] = im; o[257] = 0.f;
-                   } else {
-                     o[2 * slot] = re;
-                     o[2 * slot + 1] = im;
-                   }
-                 });
       }
+    } else {  // MODE 2: plain spectra
+      float* o = a.out + (((size_t)n * a.S + (valid ? s : 0)) * a.R + ring) * 129 * 2;
+      fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
+               [&](int slot, float re, float im) {
+                 if (!valid) return;
+                 if (slot == 0) {
+                   o[0] = re; o[1] = 0.f;
+                   o[256] = im; o[257] = 0.f;
+                 } else {
+                   o[2 * slot] = re;
+                   o[2 * slot + 1] = im;
+                 }
+               });
     }
   }
 }
@@ -204,7 +241,7 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_batch(PolarBatch b) {
 }
 
 size_t polar_lds_bytes(int Lp) {
-  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)(8 * 64 * 17 + kNphi) * sizeof(float2);
+  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)(kPolarWaves * 64 * 9 + kNphi) * sizeof(float2);
 }
 
 hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st) {
