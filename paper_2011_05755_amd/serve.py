@@ -32,6 +32,7 @@ import dataclasses
 import heapq
 import json
 import math
+import sys
 import time
 
 RESULT_BYTES_PER_PARTICLE = 8 * 4   # ref, shift_x, shift_y, psi, mirror, cc, cc2, flat_index
@@ -178,9 +179,11 @@ def percentile(xs: list[float], q: float) -> float:
 
 
 def run_trace(server: Server, arrivals: list[tuple[float, Request]], clock=time.perf_counter,
-              sleep=time.sleep) -> dict:
+              sleep=time.sleep, warmup: int = 0, progress=None) -> dict:
     """Feed `arrivals` ((offset s, request), sorted) to the server on the
-    clock, run until every request is finished; return latency statistics."""
+    clock, run until every request is finished; return latency statistics
+    over the requests after the first `warmup` arrivals.  `progress(n_done)`
+    is called as requests finish."""
     t0 = clock()
     heap = [(t, i, r) for i, (t, r) in enumerate(arrivals)]
     heapq.heapify(heap)
@@ -191,19 +194,25 @@ def run_trace(server: Server, arrivals: list[tuple[float, Request]], clock=time.
             t, _, r = heapq.heappop(heap)
             r.t_arrival = t
             server.submit(r, t)
+        done_before = len(server.finished)
         busy = server.poll(now)
+        if progress and len(server.finished) != done_before:
+            progress(len(server.finished))
         if server.inflight:
             server.wait_one()      # block on the oldest step; the next is already queued
         elif heap:
             sleep(max(0.0, min(heap[0][0] - (clock() - t0), 0.05)))
     t_end = clock() - t0
-    lat = [r.latency for r in server.finished]
-    parts = sum(r.N for r in server.finished)
-    first = min(t for t, _ in arrivals) if arrivals else 0.0
-    return dict(requests=len(server.finished), particles=parts, steps=server.steps,
+    measured = [r for r in server.finished if r.rid >= warmup]
+    lat = [r.latency for r in measured]
+    parts = sum(r.N for r in measured)
+    first = min((r.t_arrival for r in measured), default=0.0)
+    t_last = max((r.t_done for r in measured), default=t_end)
+    return dict(requests=len(measured), warmup_requests=len(server.finished) - len(measured),
+                particles=parts, steps=server.steps,
                 p50_s=percentile(lat, 50), p99_s=percentile(lat, 99), max_s=max(lat) if lat else math.nan,
                 mean_s=sum(lat) / len(lat) if lat else math.nan,
-                makespan_s=t_end - first, particles_per_s=parts / max(t_end - first, 1e-9),
+                makespan_s=t_last - first, particles_per_s=parts / max(t_last - first, 1e-9),
                 max_waiting=server.max_waiting, peak_admitted_gib=server.peak_used / 2**30)
 
 
@@ -276,25 +285,39 @@ def make_refsets(ctx, n_sets: int, seed: int, precision: str, specs=None):
 
 
 def make_requests(sets, n_req: int, rate: float, seed: int, device, n_scale: float = 1.0,
-                  host: bool = False):
+                  host: bool = False, pool: bool = False):
     """Poisson arrivals at `rate`/s; each request draws its refset uniformly
     and its size from the uneven-stack distribution (N uniform 2k..50k,
     scaled by n_scale; shift range of its refset).  host: particles in pinned
-    host memory (copied at admission), else resident on the device."""
+    host memory (copied at admission), else resident on the device.  pool:
+    every refset gets one stack of the largest size and a request takes a
+    random contiguous slice of it (for long traces that could not hold a
+    stack per request)."""
     import numpy as np
 
     from . import mra, synth
     rng = np.random.default_rng(seed)
+    n_max = max(1, int(round(50000 * n_scale)))
+    pools = {}
+    if pool:
+        for s in sets:
+            p, _ = synth.make_particles(s["blobs"], n_max, s["shift_max"], s["snr"], seed=(seed, 500 + s["id"]),
+                                        device=device)
+            pools[s["id"]] = p.cpu().pin_memory() if host else p
     t = 0.0
     out = []
     for j in range(n_req):
         t += rng.exponential(1.0 / rate)
         s = sets[int(rng.integers(len(sets)))]
         N = max(1, int(round(int(rng.integers(2000, 50001)) * n_scale)))
-        parts, _ = synth.make_particles(s["blobs"], N, s["shift_max"], s["snr"], seed=(seed, 1000 + j),
-                                        device=device)
-        if host:
-            parts = parts.cpu().pin_memory()
+        if pool:
+            o = int(rng.integers(0, n_max - N + 1))
+            parts = pools[s["id"]][o:o + N]
+        else:
+            parts, _ = synth.make_particles(s["blobs"], N, s["shift_max"], s["snr"], seed=(seed, 1000 + j),
+                                            device=device)
+            if host:
+                parts = parts.cpu().pin_memory()
         r = Request(refset_id=s["id"], N=N, L=s["L"], shift_max=s["shift_max"], parts=parts,
                     out=mra.AlignResult.empty(N, device))
         out.append((t, r))
@@ -313,6 +336,8 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--check", type=int, default=4, help="requests re-run alone and compared bit for bit")
     ap.add_argument("--host-inputs", action="store_true", help="particles in pinned host memory")
+    ap.add_argument("--warmup-requests", type=int, default=0, help="first arrivals left out of the statistics")
+    ap.add_argument("--pool", action="store_true", help="requests slice one pre-generated stack per refset")
     ap.add_argument("--workspace-gib", type=float, default=8.0, help="library workspace cap (reserved)")
     args = ap.parse_args(argv)
 
@@ -324,11 +349,20 @@ def main(argv=None) -> int:
     ws = int(args.workspace_gib * 2**30)
     ctx = mra.Context(0, workspace_cap=ws)
     sets = make_refsets(ctx, args.refsets, args.seed, args.precision)
-    arrivals = make_requests(sets, args.requests, args.rate, args.seed, dev, args.n_scale, host=args.host_inputs)
+    n_all = args.requests + args.warmup_requests
+    arrivals = make_requests(sets, n_all, args.rate, args.seed, dev, args.n_scale, host=args.host_inputs,
+                             pool=args.pool)
     torch.cuda.synchronize()
     server = Server(AlignExecutor(ctx), hbm_budget=int(args.budget_gib * 2**30), workspace_bytes=ws,
                     step_rows=args.step_rows)
-    stats = run_trace(server, arrivals)
+    t_start = time.perf_counter()
+
+    def progress(n):
+        if n % 25 == 0 or n == n_all:
+            print(f"[serve] {n}/{n_all} requests done, {time.perf_counter() - t_start:.1f} s, "
+                  f"waiting {len(server.waiting)}, active {len(server.active)}", file=sys.stderr, flush=True)
+
+    stats = run_trace(server, arrivals, warmup=args.warmup_requests, progress=progress)
     torch.cuda.synchronize()
     same = 0
     for _, r in arrivals[:args.check]:
@@ -336,8 +370,10 @@ def main(argv=None) -> int:
         a, b = alone.to_numpy(), r.out.to_numpy()
         same += all(np.array_equal(a[k], b[k]) for k in a)
     offered = sum(r.N for _, r in arrivals) / max(arrivals[-1][0], 1e-9)
-    line = dict(workload=f"serving: {args.requests} requests, Poisson {args.rate}/s, {args.refsets} resident "
-                         f"refsets, {args.precision}", offered_particles_per_s=round(offered, 1),
+    line = dict(workload=f"serving: {args.warmup_requests} warm-up + {args.requests} measured requests, Poisson "
+                         f"{args.rate}/s, {args.refsets} resident refsets, {args.precision}"
+                         + (", host inputs" if args.host_inputs else "") + (", pooled stacks" if args.pool else ""),
+                offered_particles_per_s=round(offered, 1),
                 same_alone_and_in_mix=f"{same}/{min(args.check, len(arrivals))}",
                 **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()})
     print(json.dumps(line), flush=True)
