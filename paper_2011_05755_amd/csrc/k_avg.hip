@@ -88,28 +88,46 @@ __global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
   int end = start + kAvgChunk;
   if (end > a.cls_start[k + 1]) end = a.cls_start[k + 1];
   const int L = a.L, L2 = L * L;
+  // each thread's pixels u = tid + i * kAvgThreads; the next particle's
+  // pixels are loaded into registers while the current one is warped
+  float nxt[PPT];
+  auto fetch = [&](int pi) {
+    const float* src = a.parts + (size_t)a.order[pi] * L2;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int u = threadIdx.x + i * kAvgThreads;
+      nxt[i] = u < L2 ? __builtin_nontemporal_load(src + u) : 0.f;
+    }
+  };
   double acc[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) acc[i] = 0.0;
+  if (start < end) fetch(start);
   for (int pi = start; pi < end; ++pi) {
     const int n = a.order[pi];
+    __syncthreads();  // the previous particle's warp has finished reading img
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int u = threadIdx.x + i * kAvgThreads;
+      if (u < L2) img[u] = nxt[i];
+    }
     __syncthreads();
-    const float* src = a.parts + (size_t)n * L2;
-    for (int i = threadIdx.x; i < L2; i += kAvgThreads) img[i] = src[i];
-    __syncthreads();
-    const double2 cs = a.cs64[a.psi[n] & 255];
-    const double sx = a.shift_x[n], sy = a.shift_y[n];
-    const double msign = a.mirror[n] ? -1.0 : 1.0;
+    if (pi + 1 < end) fetch(pi + 1);
+    // sample position c + s + Mir^m Rot(psi)(u - c), in FP32 (positions are
+    // below 2^8, so the bilinear fractions carry ~1e-5 px of rounding)
+    const double2 cs64 = a.cs64[a.psi[n] & 255];
+    const float cs = (float)cs64.x, sn = (float)cs64.y;
+    const float ox = (float)(a.cx + a.shift_x[n]), oy = (float)(a.cx + a.shift_y[n]);
+    const float msign = a.mirror[n] ? -1.f : 1.f;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       const int u = threadIdx.x + i * kAvgThreads;
       if (u < L2) {
-        const double vx = (double)(u % L - a.cx), vy = (double)(u / L - a.cx);
-        const double rx = cs.x * vx - cs.y * vy;
-        const double ry = msign * (cs.y * vx + cs.x * vy);
-        const double X = a.cx + sx + rx, Y = a.cx + sy + ry;
-        const double x0 = floor(X), y0 = floor(Y);
-        const float fx = (float)(X - x0), fy = (float)(Y - y0);
+        const float vx = (float)(u % L - a.cx), vy = (float)(u / L - a.cx);
+        const float X = ox + (cs * vx - sn * vy);
+        const float Y = oy + msign * (sn * vx + cs * vy);
+        const float x0 = floorf(X), y0 = floorf(Y);
+        const float fx = X - x0, fy = Y - y0;
         const int ix = (int)x0, iy = (int)y0;
         const bool in_x0 = ix >= 0 && ix < L, in_x1 = ix + 1 >= 0 && ix + 1 < L;
         const bool in_y0 = iy >= 0 && iy < L, in_y1 = iy + 1 >= 0 && iy + 1 < L;
@@ -153,7 +171,9 @@ hipError_t launch_averages(const AvgArgs& a, hipStream_t st) {
   const int ppt = (L2 + kAvgThreads - 1) / kAvgThreads;
   dim3 g(a.max_chunks), b(kAvgThreads);
   if (ppt <= 16) hipLaunchKernelGGL(k_avg_accum<16>, g, b, lds, st, a);
+  else if (ppt <= 24) hipLaunchKernelGGL(k_avg_accum<24>, g, b, lds, st, a);
   else if (ppt <= 32) hipLaunchKernelGGL(k_avg_accum<32>, g, b, lds, st, a);
+  else if (ppt <= 48) hipLaunchKernelGGL(k_avg_accum<48>, g, b, lds, st, a);
   else if (ppt <= 64) hipLaunchKernelGGL(k_avg_accum<64>, g, b, lds, st, a);
   else hipLaunchKernelGGL(k_avg_accum<100>, g, b, lds, st, a);
   const int64_t nf = (int64_t)a.K * L2;
