@@ -84,6 +84,12 @@ void* alloc(mra_ctx* c, size_t bytes, const char* what) {
 void* ws_get(mra_ctx* c, const std::string& name, size_t bytes) {
   DevBuf& b = c->ws[name];
   if (b.bytes < bytes) {
+    uint64_t total = bytes;  // the workspace after this buffer grows
+    for (const auto& kv : c->ws)
+      if (&kv.second != &b) total += kv.second.bytes;
+    if (total > c->cap)
+      throw Fail{MRA_E_NOMEM, "workspace cap of " + std::to_string(c->cap) + " bytes is too small (" + name +
+                                  " needs " + std::to_string(bytes) + " bytes)"};
     if (b.p) hip_check(c, hipFree(b.p), "hipFree");
     b.p = nullptr;
     b.bytes = 0;
@@ -198,7 +204,7 @@ size_t a_bytes_per_row(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * 
 
 int64_t chunk_particles(mra_ctx* c, const Refset& rs, const Plan& p) {
   if (rs.chunk > 0) return rs.chunk;
-  const uint64_t budget = std::max<uint64_t>(c->cap / 2, 64ull << 20);
+  const uint64_t budget = c->cap / 2;
   const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
   int64_t n = (int64_t)(budget / per);
   return std::max<int64_t>(n, 1);
@@ -408,7 +414,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
 }
 
 void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Plan>& plans) {
-  const uint64_t budget = std::max<uint64_t>(c->cap / 2, 64ull << 20);
+  const uint64_t budget = c->cap / 2;
   // stacks that share a correlation instantiation (precision, tile variant)
   // are packed into the same waves; within a group the caller's order holds
   std::vector<int> order(n);
