@@ -277,9 +277,9 @@ def test_error_codes(ctx):
     ctx.load_refs(33, refs, r_min=1, r_max=10, shift_max=1)
     empty = torch.empty((0, 32, 32), device=DEV)
     ctx.align(33, empty, out=mra.AlignResult.empty(0, DEV))    # N = 0 is a no-op
-    small = mra.Context(0, workspace_cap=1 << 20)     # 1 MiB: less than one particle's operand
-    small.load_refs(0, refs, r_min=1, r_max=10, shift_max=1)
-    with pytest.raises(mra.MRAError) as e:
+    small = mra.Context(0, workspace_cap=1 << 16)     # 64 KiB: less than one row tile of the operand (98 KiB)
+    with pytest.raises(mra.MRAError) as e:            # reference preparation or the alignment runs out
+        small.load_refs(0, refs, r_min=1, r_max=10, shift_max=1)
         small.align(0, parts)
     assert e.value.code == mra.MRA_E_NOMEM
     small.close()
