@@ -10,7 +10,8 @@ float64 (see ``mra_oracle``): bilinear polar resampling of every shifted and
 mirrored particle, the ring-weighted rotational cross-correlation of Sec. 2 as
 a direct sum over rings and angles (no FFT), the arg-max over
 (reference, mirror, shift, angle) of Algorithm 1, and the class-average update
-of Algorithm 1 ("compute new Y' from aligned images").
+of Algorithm 1 (new references Y' built from the aligned images), and the outer loop
+that feeds the averages back as references until few particles change class.
 """
 
 from .mra_oracle import (  # noqa: F401
@@ -21,6 +22,7 @@ from .mra_oracle import (  # noqa: F401
     candidate_cc,
     cc_table,
     centre,
+    classify,
     flat_index,
     particle_polar,
     polar_positions,

@@ -311,3 +311,34 @@ def averages(parts: np.ndarray, params: dict, prev: np.ndarray, g: Geometry):
         if counts[k] > 0:
             out[k] = sums[k] / counts[k]
     return out, counts
+
+
+def classify(parts: np.ndarray, refs: np.ndarray, g: Geometry, max_iter: int = 20,
+             max_changed_frac: float = 0.005):
+    """Iterative MRA: the outer loop of Algorithm 1 (align every image against
+    the current references, replace the references by the class averages of
+    the aligned images, repeat until convergence).
+
+    The paper fixes no convergence rule.  Reading used: stop after a pass in
+    which the fraction of particles whose class (ref) differs from the
+    previous pass is at most ``max_changed_frac``, or after ``max_iter``
+    passes.  The averages enter the next pass as float32 images (the type in
+    which references are handed to a pass).  Returns (params of the last pass,
+    averages after it [K, L, L] float32, counts, passes run, the changed
+    fractions of passes 2, 3, ...).
+    """
+    Y = np.asarray(refs, dtype=np.float32)
+    prev = None
+    fracs = []
+    params, counts, it = None, None, 0
+    for it in range(1, max_iter + 1):
+        params = align(parts, Y, g)
+        Yn, counts = averages(parts, params, Y, g)
+        Y = Yn.astype(np.float32)
+        if prev is not None:
+            frac = float(np.mean(params["ref"] != prev))
+            fracs.append(frac)
+            if frac <= max_changed_frac:
+                break
+        prev = params["ref"].copy()
+    return params, Y, counts, it, fracs
