@@ -322,7 +322,8 @@ def classify(parts: np.ndarray, refs: np.ndarray, g: Geometry, max_iter: int = 2
     The paper fixes no convergence rule.  Reading used: stop after a pass in
     which the fraction of particles whose class (ref) differs from the
     previous pass is at most ``max_changed_frac``, or after ``max_iter``
-    passes.  The averages enter the next pass as float32 images (the type in
+    passes (the test is made on the count: changed <= max_changed_frac * N).
+    The averages enter the next pass as float32 images (the type in
     which references are handed to a pass).  Returns (params of the last pass,
     averages after it [K, L, L] float32, counts, passes run, the changed
     fractions of passes 2, 3, ...).
@@ -336,9 +337,9 @@ def classify(parts: np.ndarray, refs: np.ndarray, g: Geometry, max_iter: int = 2
         Yn, counts = averages(parts, params, Y, g)
         Y = Yn.astype(np.float32)
         if prev is not None:
-            frac = float(np.mean(params["ref"] != prev))
-            fracs.append(frac)
-            if frac <= max_changed_frac:
+            n_changed = int(np.count_nonzero(params["ref"] != prev))
+            fracs.append(n_changed / len(prev))
+            if n_changed <= max_changed_frac * len(prev):
                 break
         prev = params["ref"].copy()
     return params, Y, counts, it, fracs
