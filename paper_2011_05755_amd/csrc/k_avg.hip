@@ -1,6 +1,6 @@
-// Class-average update (Algorithm 1: "find the corresponding alignment
-// parameters and apply them to each image", "compute new Y' from aligned
-// images").  Each particle is warped back into its reference frame,
+// Class-average update (Algorithm 1: each image is transformed by its
+// alignment parameters and the aligned images of a class give its new
+// reference Y').  Each particle is warped back into its reference frame,
 //   aligned(u) = Bil(X; c + s + Mir^m Rot(psi 2 pi / 256)(u - c)),
 // and summed per class.  The sum runs in a fixed order so the result does
 // not depend on scheduling:

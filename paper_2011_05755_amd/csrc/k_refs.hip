@@ -1,5 +1,5 @@
-// Reference preparation (Algorithm 1: "convert y_i to polar coordinates and
-// apply FFT to obtain y'_i"), done once per reference set in FP64:
+// Reference preparation (Algorithm 1: each reference resampled to polar
+// coordinates and transformed per ring), done once per reference set in FP64:
 //   q_k[r][j]  bilinear polar samples at zero shift,
 //   nu_k       weighted ring norm sqrt(sum_r w_r sum_j q^2),
 //   Q_k[r][f]  per-ring DFT (direct sum), times w_r / (nu_k * 256),

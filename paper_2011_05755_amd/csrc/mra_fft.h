@@ -1,8 +1,7 @@
 // Small fixed-size complex DFTs used by the ring transforms.
 //
-// The per-ring forward transform (Algorithm 1: "convert to polar
-// coordinates and apply FFT") and the inverse transform over angle of the
-// correlation spectra (Sec. 3: "apply inverse FFT to CC table") are built
+// The per-ring forward transform of the polar samples (Algorithm 1) and
+// the inverse transform over angle of the correlation spectra (Sec. 3) are built
 // from 4-, 8- and 16-point DFTs evaluated in registers.  SIGN = -1 is the
 // forward kernel exp(-2 pi i k n / N), SIGN = +1 the inverse kernel
 // exp(+2 pi i k n / N) (unnormalised).  Inputs and outputs are in natural
