@@ -2,8 +2,8 @@
  * mra.h -- C ABI of libmra.so: one multi-reference-alignment (MRA) pass of
  * 2-D classification on an AMD Instinct MI355X (gfx950).
  *
- * The calls follow the problem statement of Algorithm 1 ("GPU Accelerated
- * MRA"): input a set of particle images X and a set of reference images Y;
+ * The calls follow the problem statement of Algorithm 1 (the GPU MRA
+ * pass): input a set of particle images X and a set of reference images Y;
  * output the class averages Y' and the alignment parameters of every image.
  * The similarity is the ring-weighted rotational cross-correlation of Sec. 2,
  *     c(phi) = int_{r1}^{r2} int_0^{2 pi} x(r, theta) y(r, theta + phi) |r| dtheta dr,
@@ -150,6 +150,31 @@ int mra_align(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
  * in a fixed order, so the result is deterministic. */
 int mra_update_averages(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
                         const mra_result* params, float* averages, int32_t* counts);
+
+/* Iterative MRA: the outer repeat of Algorithm 1 (Sec. 2: align against
+ * the current averages, assign each particle the best reference, rebuild
+ * the averages, iterate).  Pass i loads `averages` as the references of
+ * `refset_id` (geometry `g`, K classes; a tuning set on that id carries over
+ * when its geometry and K equal these), aligns all N particles into `out`
+ * and updates `averages` and `counts` as mra_update_averages does.  The
+ * paper gives no convergence rule; this one stops after pass i >= 2 when at
+ * most max_changed_frac * N particles changed class since pass i - 1, or
+ * after max_iter passes.
+ *  averages   float32 [K][L][L] device, in: initial references, out: the
+ *             averages after the last pass
+ *  out        the last pass's parameters (cc2, if non-NULL, costs a second
+ *             contraction on every pass)
+ *  counts     int32 [K] device: class sizes of the last pass
+ *  n_iter     host: passes run
+ *  changed    host int64 [max_iter] or NULL: changed[i-1] = particles whose
+ *             class differs from pass i-1 (changed[0] = N)
+ * On return the refset holds the references of the last pass (not the new
+ * averages).  Synchronises the stream once per pass.  Errors: MRA_E_INVAL
+ * (N < 1, max_iter < 1, max_changed_frac outside [0, 1], NULL pointers,
+ * bad geometry), and those of mra_load_refs and mra_align. */
+int mra_classify(mra_ctx* ctx, int32_t refset_id, const mra_geom* g, const float* parts, int64_t N,
+                 float* averages, int32_t K, int32_t max_iter, double max_changed_frac,
+                 mra_result* out, int32_t* counts, int32_t* n_iter, int64_t* changed);
 
 /* Alignment of several stacks of uneven size (each against its own refset,
  * with its own shift range) in one call.  Stacks are cut into pieces that

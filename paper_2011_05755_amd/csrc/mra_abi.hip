@@ -458,6 +458,124 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
   if (!wave.empty()) launch_wave(c, stacks, wave);
 }
 
+void load_refs_impl(mra_ctx* c, int32_t id, const float* refs, int32_t K, const mra_geom* g) {
+  check_geom(g);
+  if (K < 1) throw Fail{MRA_E_INVAL, "K must be >= 1"};
+  if (!refs) throw Fail{MRA_E_INVAL, "refs is NULL"};
+  Refset rs;
+  rs.g = *g;
+  rs.K = K;
+  rs.R = g->r_max - g->r_min + 1;
+  rs.R4 = (rs.R + 3) / 4;
+  rs.NS = (rs.R4 + 7) / 8;
+  rs.n_kt = (K + kRefTile - 1) / kRefTile;
+  rs.variant = corr_default_variant(g->precision, rs.R4);
+  hipStream_t st = c->stream;
+  try {
+    // particle sampling stencil, exactly symmetric in j <-> 256 - j
+    std::vector<double> cs, sn;
+    build_cs(kNphi, cs, sn);
+    std::vector<Stencil> sten((size_t)rs.R * kNphi);
+    rs.dmin = 0;
+    rs.dmax = 0;
+    for (int r = 0; r < rs.R; ++r)
+      for (int j = 0; j < kNphi; ++j) {
+        const double rr = g->r_min + r;
+        const double x = rr * cs[j], y = rr * sn[j];
+        const double fx = std::floor(x), fy = std::floor(y);
+        Stencil s;
+        s.dx = (int)fx;
+        s.dy = (int)fy;
+        s.fx = (float)(x - fx);
+        s.fy = (float)(y - fy);
+        sten[(size_t)r * kNphi + j] = s;
+        rs.dmin = std::min({rs.dmin, s.dx, s.dy});
+        rs.dmax = std::max({rs.dmax, s.dx, s.dy});
+      }
+    rs.stencil = (Stencil*)alloc(c, sten.size() * sizeof(Stencil), "stencil");
+    hip_check(c, hipMemcpyAsync(rs.stencil, sten.data(), sten.size() * sizeof(Stencil), hipMemcpyHostToDevice, st), "memcpy");
+
+    RefArgs ra{};
+    ra.refs = refs;
+    ra.K = K; ra.L = g->L; ra.r_min = g->r_min; ra.R = rs.R; ra.R4 = rs.R4; ra.NS = rs.NS;
+    ra.n_ref_tiles = rs.n_kt; ra.normalize = g->normalize; ra.prec = g->precision;
+    ra.cs64 = c->cs64;
+    ra.q64 = (double*)ws_get(c, "ref_q64", (size_t)K * rs.R * kNphi * sizeof(double));
+    ra.inv = (double*)ws_get(c, "ref_inv", (size_t)K * sizeof(double));
+    ra.Qs = (double2*)ws_get(c, "ref_Qs", (size_t)K * 129 * rs.R * sizeof(double2));
+    ra.bmax = (float*)ws_get(c, "ref_bmax", 256);
+    rs.norm = (double*)alloc(c, (size_t)K * sizeof(double), "norm");
+    rs.qhat = (float*)alloc(c, (size_t)K * rs.R * kNphi * sizeof(float), "qhat");
+    ra.norm = rs.norm;
+    ra.qhat32 = rs.qhat;
+    hip_check(c, hipMemsetAsync(ra.bmax, 0, sizeof(float), st), "memset");
+    hip_check(c, launch_ref_stage1(ra, st), "ref stage 1");
+    std::vector<double> norms(K);
+    float bmax = 0.f;
+    hip_check(c, hipMemcpyAsync(norms.data(), rs.norm, K * sizeof(double), hipMemcpyDeviceToHost, st), "memcpy");
+    hip_check(c, hipMemcpyAsync(&bmax, ra.bmax, sizeof(float), hipMemcpyDeviceToHost, st), "memcpy");
+    hip_check(c, hipStreamSynchronize(st), "sync");
+    if (g->normalize)
+      for (int k = 0; k < K; ++k)
+        if (!(norms[k] > 0.0))
+          throw Fail{MRA_E_DEGENERATE, "reference " + std::to_string(k) + " has zero weighted ring norm"};
+    rs.b_scale = 1.f;
+    if (g->precision == kFP16 && bmax > 0.f) rs.b_scale = std::ldexp(1.f, 14 - (int)std::ceil(std::log2(bmax)));
+    ra.b_scale = rs.b_scale;
+    if (g->precision == kFP32)
+      rs.B32 = (float*)alloc(c, (size_t)rs.n_kt * kSlots * rs.R4 * 64 * sizeof(float), "B32");
+    else
+      rs.B16 = (uint16_t*)alloc(c, (size_t)rs.n_kt * kSlots * rs.NS * 64 * 8 * sizeof(uint16_t), "B16");
+    ra.B32 = rs.B32;
+    ra.B16 = rs.B16;
+    hip_check(c, launch_ref_stage2(ra, st), "ref stage 2");
+  } catch (...) {
+    free_refset(rs);
+    throw;
+  }
+  auto it = c->refs.find(id);
+  if (it != c->refs.end()) {
+    hip_check(c, hipStreamSynchronize(st), "sync");
+    free_refset(it->second);
+    c->refs.erase(it);
+  }
+  c->refs[id] = rs;
+}
+
+void update_averages_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, const mra_result* params,
+                          float* averages, int32_t* counts) {
+  Refset& rs = get_refset(c, id);
+  if (N < 0 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
+  if (!averages || !counts) throw Fail{MRA_E_INVAL, "averages and counts must be non-NULL"};
+  if (!params || !params->ref || !params->shift_x || !params->shift_y || !params->psi || !params->mirror)
+    throw Fail{MRA_E_INVAL, "params arrays must be non-NULL"};
+  if (N > 0 && !parts) throw Fail{MRA_E_INVAL, "parts is NULL"};
+  hipStream_t st = c->stream;
+  const int K = rs.K, L = rs.g.L;
+  if (N == 0) {
+    hip_check(c, hipMemsetAsync(counts, 0, K * sizeof(int32_t), st), "memset");
+    return;
+  }
+  AvgArgs a{};
+  a.parts = parts;
+  a.N = N;
+  a.K = K; a.L = L; a.cx = L / 2;
+  a.ref = params->ref; a.shift_x = params->shift_x; a.shift_y = params->shift_y;
+  a.psi = params->psi; a.mirror = params->mirror;
+  a.cs64 = c->cs64;
+  a.n_blk = (int)((N + 1023) / 1024);
+  a.max_chunks = (int)((N + kAvgChunk - 1) / kAvgChunk) + K;
+  a.blk_cnt = (int*)ws_get(c, "avg_blk_cnt", (size_t)a.n_blk * K * sizeof(int));
+  a.blk_off = (int*)ws_get(c, "avg_blk_off", (size_t)a.n_blk * K * sizeof(int));
+  a.cls_start = (int*)ws_get(c, "avg_cls", (size_t)(K + 1) * sizeof(int));
+  a.chunk_start = (int*)ws_get(c, "avg_chunk", (size_t)(K + 1) * sizeof(int));
+  a.order = (int*)ws_get(c, "avg_order", (size_t)N * sizeof(int));
+  a.partial = (float*)ws_get(c, "avg_partial", (size_t)a.max_chunks * L * L * sizeof(float));
+  a.averages = averages;
+  a.counts = counts;
+  timed(c, "averages", [&] { hip_check(c, launch_averages(a, st), "averages"); });
+}
+
 template <class F>
 int guard(mra_ctx* c, F&& fn) {
   if (!c) return MRA_E_INVAL;
@@ -540,89 +658,7 @@ int mra_destroy(mra_ctx* c) {
 }
 
 int mra_load_refs(mra_ctx* c, int32_t id, const float* refs, int32_t K, const mra_geom* g) {
-  return guard(c, [&] {
-    check_geom(g);
-    if (K < 1) throw Fail{MRA_E_INVAL, "K must be >= 1"};
-    if (!refs) throw Fail{MRA_E_INVAL, "refs is NULL"};
-    Refset rs;
-    rs.g = *g;
-    rs.K = K;
-    rs.R = g->r_max - g->r_min + 1;
-    rs.R4 = (rs.R + 3) / 4;
-    rs.NS = (rs.R4 + 7) / 8;
-    rs.n_kt = (K + kRefTile - 1) / kRefTile;
-    rs.variant = corr_default_variant(g->precision, rs.R4);
-    hipStream_t st = c->stream;
-    try {
-      // particle sampling stencil, exactly symmetric in j <-> 256 - j
-      std::vector<double> cs, sn;
-      build_cs(kNphi, cs, sn);
-      std::vector<Stencil> sten((size_t)rs.R * kNphi);
-      rs.dmin = 0;
-      rs.dmax = 0;
-      for (int r = 0; r < rs.R; ++r)
-        for (int j = 0; j < kNphi; ++j) {
-          const double rr = g->r_min + r;
-          const double x = rr * cs[j], y = rr * sn[j];
-          const double fx = std::floor(x), fy = std::floor(y);
-          Stencil s;
-          s.dx = (int)fx;
-          s.dy = (int)fy;
-          s.fx = (float)(x - fx);
-          s.fy = (float)(y - fy);
-          sten[(size_t)r * kNphi + j] = s;
-          rs.dmin = std::min({rs.dmin, s.dx, s.dy});
-          rs.dmax = std::max({rs.dmax, s.dx, s.dy});
-        }
-      rs.stencil = (Stencil*)alloc(c, sten.size() * sizeof(Stencil), "stencil");
-      hip_check(c, hipMemcpyAsync(rs.stencil, sten.data(), sten.size() * sizeof(Stencil), hipMemcpyHostToDevice, st), "memcpy");
-
-      RefArgs ra{};
-      ra.refs = refs;
-      ra.K = K; ra.L = g->L; ra.r_min = g->r_min; ra.R = rs.R; ra.R4 = rs.R4; ra.NS = rs.NS;
-      ra.n_ref_tiles = rs.n_kt; ra.normalize = g->normalize; ra.prec = g->precision;
-      ra.cs64 = c->cs64;
-      ra.q64 = (double*)ws_get(c, "ref_q64", (size_t)K * rs.R * kNphi * sizeof(double));
-      ra.inv = (double*)ws_get(c, "ref_inv", (size_t)K * sizeof(double));
-      ra.Qs = (double2*)ws_get(c, "ref_Qs", (size_t)K * 129 * rs.R * sizeof(double2));
-      ra.bmax = (float*)ws_get(c, "ref_bmax", 256);
-      rs.norm = (double*)alloc(c, (size_t)K * sizeof(double), "norm");
-      rs.qhat = (float*)alloc(c, (size_t)K * rs.R * kNphi * sizeof(float), "qhat");
-      ra.norm = rs.norm;
-      ra.qhat32 = rs.qhat;
-      hip_check(c, hipMemsetAsync(ra.bmax, 0, sizeof(float), st), "memset");
-      hip_check(c, launch_ref_stage1(ra, st), "ref stage 1");
-      std::vector<double> norms(K);
-      float bmax = 0.f;
-      hip_check(c, hipMemcpyAsync(norms.data(), rs.norm, K * sizeof(double), hipMemcpyDeviceToHost, st), "memcpy");
-      hip_check(c, hipMemcpyAsync(&bmax, ra.bmax, sizeof(float), hipMemcpyDeviceToHost, st), "memcpy");
-      hip_check(c, hipStreamSynchronize(st), "sync");
-      if (g->normalize)
-        for (int k = 0; k < K; ++k)
-          if (!(norms[k] > 0.0))
-            throw Fail{MRA_E_DEGENERATE, "reference " + std::to_string(k) + " has zero weighted ring norm"};
-      rs.b_scale = 1.f;
-      if (g->precision == kFP16 && bmax > 0.f) rs.b_scale = std::ldexp(1.f, 14 - (int)std::ceil(std::log2(bmax)));
-      ra.b_scale = rs.b_scale;
-      if (g->precision == kFP32)
-        rs.B32 = (float*)alloc(c, (size_t)rs.n_kt * kSlots * rs.R4 * 64 * sizeof(float), "B32");
-      else
-        rs.B16 = (uint16_t*)alloc(c, (size_t)rs.n_kt * kSlots * rs.NS * 64 * 8 * sizeof(uint16_t), "B16");
-      ra.B32 = rs.B32;
-      ra.B16 = rs.B16;
-      hip_check(c, launch_ref_stage2(ra, st), "ref stage 2");
-    } catch (...) {
-      free_refset(rs);
-      throw;
-    }
-    auto it = c->refs.find(id);
-    if (it != c->refs.end()) {
-      hip_check(c, hipStreamSynchronize(st), "sync");
-      free_refset(it->second);
-      c->refs.erase(it);
-    }
-    c->refs[id] = rs;
-  });
+  return guard(c, [&] { load_refs_impl(c, id, refs, K, g); });
 }
 
 int mra_unload_refs(mra_ctx* c, int32_t id) {
@@ -667,37 +703,58 @@ int mra_align_batch(mra_ctx* c, const mra_stack* stacks, int32_t n) {
 
 int mra_update_averages(mra_ctx* c, int32_t id, const float* parts, int64_t N, const mra_result* params,
                         float* averages, int32_t* counts) {
+  return guard(c, [&] { update_averages_impl(c, id, parts, N, params, averages, counts); });
+}
+
+int mra_classify(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts, int64_t N, float* averages,
+                 int32_t K, int32_t max_iter, double max_changed_frac, mra_result* out, int32_t* counts,
+                 int32_t* n_iter, int64_t* changed) {
   return guard(c, [&] {
-    Refset& rs = get_refset(c, id);
-    if (N < 0 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
-    if (!averages || !counts) throw Fail{MRA_E_INVAL, "averages and counts must be non-NULL"};
-    if (!params || !params->ref || !params->shift_x || !params->shift_y || !params->psi || !params->mirror)
-      throw Fail{MRA_E_INVAL, "params arrays must be non-NULL"};
-    if (N > 0 && !parts) throw Fail{MRA_E_INVAL, "parts is NULL"};
-    hipStream_t st = c->stream;
-    const int K = rs.K, L = rs.g.L;
-    if (N == 0) {
-      hip_check(c, hipMemsetAsync(counts, 0, K * sizeof(int32_t), st), "memset");
-      return;
+    check_geom(g);
+    if (K < 1) throw Fail{MRA_E_INVAL, "K must be >= 1"};
+    if (N < 1 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
+    if (!parts || !averages || !counts || !n_iter) throw Fail{MRA_E_INVAL, "NULL argument"};
+    if (max_iter < 1) throw Fail{MRA_E_INVAL, "max_iter must be >= 1"};
+    if (!(max_changed_frac >= 0.0 && max_changed_frac <= 1.0))
+      throw Fail{MRA_E_INVAL, "max_changed_frac must lie in [0, 1]"};
+    check_result(out);
+    // a tuning set on this refset id carries over when the geometry matches
+    int variant = -1, chunk = 0;
+    auto old = c->refs.find(id);
+    if (old != c->refs.end() && old->second.K == K && std::memcmp(&old->second.g, g, sizeof(mra_geom)) == 0) {
+      variant = old->second.variant;
+      chunk = old->second.chunk;
     }
-    AvgArgs a{};
-    a.parts = parts;
-    a.N = N;
-    a.K = K; a.L = L; a.cx = L / 2;
-    a.ref = params->ref; a.shift_x = params->shift_x; a.shift_y = params->shift_y;
-    a.psi = params->psi; a.mirror = params->mirror;
-    a.cs64 = c->cs64;
-    a.n_blk = (int)((N + 1023) / 1024);
-    a.max_chunks = (int)((N + kAvgChunk - 1) / kAvgChunk) + K;
-    a.blk_cnt = (int*)ws_get(c, "avg_blk_cnt", (size_t)a.n_blk * K * sizeof(int));
-    a.blk_off = (int*)ws_get(c, "avg_blk_off", (size_t)a.n_blk * K * sizeof(int));
-    a.cls_start = (int*)ws_get(c, "avg_cls", (size_t)(K + 1) * sizeof(int));
-    a.chunk_start = (int*)ws_get(c, "avg_chunk", (size_t)(K + 1) * sizeof(int));
-    a.order = (int*)ws_get(c, "avg_order", (size_t)N * sizeof(int));
-    a.partial = (float*)ws_get(c, "avg_partial", (size_t)a.max_chunks * L * L * sizeof(float));
-    a.averages = averages;
-    a.counts = counts;
-    timed(c, "averages", [&] { hip_check(c, launch_averages(a, st), "averages"); });
+    hipStream_t st = c->stream;
+    int32_t* prev = (int32_t*)ws_get(c, "cls_prev", (size_t)N * sizeof(int32_t));
+    int* cnt = (int*)ws_get(c, "cls_count", 256);
+    *n_iter = 0;
+    for (int it = 1; it <= max_iter; ++it) {
+      load_refs_impl(c, id, averages, K, g);
+      if (variant >= 0) {
+        Refset& rs = c->refs[id];
+        rs.variant = variant;
+        rs.chunk = chunk;
+      }
+      align_impl(c, id, parts, N, -1, out, nullptr);
+      int64_t n_changed = N;
+      if (it == 1) {
+        hip_check(c, hipMemcpyAsync(prev, out->ref, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, st),
+                  "memcpy");
+      } else {
+        int h = 0;
+        hip_check(c, hipMemsetAsync(cnt, 0, sizeof(int), st), "memset");
+        hip_check(c, launch_count_changed(out->ref, prev, (int)N, cnt, st), "count changed");
+        hip_check(c, hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, st), "memcpy");
+        hip_check(c, hipStreamSynchronize(st), "sync");
+        n_changed = h;
+      }
+      update_averages_impl(c, id, parts, N, out, averages, counts);
+      if (changed) changed[it - 1] = n_changed;
+      *n_iter = it;
+      if (it > 1 && (double)n_changed <= max_changed_frac * (double)N) break;
+    }
+    hip_check(c, hipStreamSynchronize(st), "sync");
   });
 }
 

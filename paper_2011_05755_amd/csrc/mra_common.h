@@ -123,6 +123,8 @@ hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st);
 hipError_t launch_merge_batch(const MergeBatch& b, hipStream_t st);
 hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st);
 hipError_t launch_part_maxabs(const float* x, int n_part, int L, float* out, hipStream_t st);
+// count[0] += #{i : cls[i] != prev[i]}; then prev = cls
+hipError_t launch_count_changed(const int32_t* cls, int32_t* prev, int n, int* count, hipStream_t st);
 
 // reference preparation
 struct RefArgs {

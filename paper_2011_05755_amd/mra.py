@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = (
     "mra_create", "mra_destroy", "mra_load_refs", "mra_unload_refs", "mra_refset_info",
-    "mra_align", "mra_update_averages", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
+    "mra_align", "mra_update_averages", "mra_classify", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
     "mra_debug_polar",
     "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_profile", "mra_profile_read",
     "mra_last_error", "mra_strerror",
@@ -74,6 +74,8 @@ def load_library() -> ctypes.CDLL:
         "mra_refset_info": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(Geom)],
         "mra_align": [vp, i32, vp, i64, ctypes.POINTER(Result)],
         "mra_update_averages": [vp, i32, vp, i64, ctypes.POINTER(Result), vp, vp],
+        "mra_classify": [vp, i32, ctypes.POINTER(Geom), vp, i64, vp, i32, i32, ctypes.c_double,
+                         ctypes.POINTER(Result), vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "mra_align_batch": [vp, ctypes.POINTER(Stack), i32],
         "mra_set_tuning": [vp, i32, ctypes.POINTER(Tuning)],
         "mra_get_tuning": [vp, i32, ctypes.POINTER(Tuning)],
@@ -245,6 +247,31 @@ class Context:
         self._check(self.lib.mra_update_averages(self._h, refset_id, _ptr(parts), parts.shape[0],
                                                  ctypes.byref(p), _ptr(averages), _ptr(counts)))
         return counts
+
+    def classify(self, refset_id: int, parts: torch.Tensor, averages: torch.Tensor, r_min: int, r_max: int,
+                 shift_max: int, max_iter: int = 20, max_changed_frac: float = 0.005, n_phi: int = 256,
+                 mirror: bool = True, precision: str = "fp32", normalize: bool = True,
+                 out: AlignResult | None = None, with_cc2: bool = False):
+        """Iterative MRA (mra_classify): averages [K, L, L] in place (initial
+        references in, final averages out).  Returns (params of the last
+        pass, counts [K], passes run, changed-per-pass list)."""
+        L = averages.shape[-1]
+        _check_images(parts, L, "parts")
+        _check_images(averages, L, "averages")
+        N, K = parts.shape[0], averages.shape[0]
+        if out is None:
+            out = AlignResult.empty(N, parts.device, with_cc2=with_cc2)
+        counts = torch.empty(K, dtype=torch.int32, device=parts.device)
+        g = Geom(L, r_min, r_max, n_phi, shift_max, int(mirror), PRECISIONS[precision], int(normalize))
+        res = out.c_struct()
+        n_iter = ctypes.c_int32()
+        changed = (ctypes.c_int64 * max(1, max_iter))()
+        self._check(self.lib.mra_classify(self._h, refset_id, ctypes.byref(g), _ptr(parts), N, _ptr(averages), K,
+                                          max_iter, max_changed_frac, ctypes.byref(res), _ptr(counts),
+                                          ctypes.byref(n_iter), changed))
+        self.refsets[refset_id] = Refset(refset_id, K, L, r_min, r_max, n_phi, shift_max, int(mirror), precision,
+                                         int(normalize))
+        return out, counts, n_iter.value, list(changed[:n_iter.value])
 
     # ---- tile configuration (see include/mra.h, mra_tuning) ----
     def set_tuning(self, refset_id: int, corr_variant: int = -1, chunk_particles: int = 0):
