@@ -11,7 +11,8 @@ mirrored particle, the ring-weighted rotational cross-correlation of Sec. 2 as
 a direct sum over rings and angles (no FFT), the arg-max over
 (reference, mirror, shift, angle) of Algorithm 1, and the class-average update
 of Algorithm 1 (new references Y' built from the aligned images), and the outer loop
-that feeds the averages back as references until few particles change class.
+that feeds the averages back as references until few particles change class;
+reference-free alignment (RFA) is the same loop with one running average.
 """
 
 from .mra_oracle import (  # noqa: F401
@@ -28,6 +29,7 @@ from .mra_oracle import (  # noqa: F401
     polar_positions,
     polar_samples,
     reference_polar,
+    rfa,
     ring_radii,
     ring_weights,
     rolled_reference_matrix,

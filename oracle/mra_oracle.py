@@ -343,3 +343,42 @@ def classify(parts: np.ndarray, refs: np.ndarray, g: Geometry, max_iter: int = 2
                 break
         prev = params["ref"].copy()
     return params, Y, counts, it, fracs
+
+
+def rfa(parts: np.ndarray, g: Geometry, max_iter: int = 10, max_changed_frac: float = 0.0,
+        init: np.ndarray | None = None):
+    """Reference-free alignment (RFA, the routine of GPU ISAC that the paper
+    builds its MRA on and benchmarks beside it, Sec. 2 and Sec. 5): every
+    particle is aligned against one running average, which is then rebuilt
+    from the aligned particles, and the two steps repeat.  It is the MRA pass
+    and average update with a single reference.
+
+    The paper does not spell the routine out.  Readings used: the first
+    reference is the plain mean of the unaligned particles (``init``
+    overrides it); every pass searches the whole shift grid around the box
+    centre, both mirrors and all angles (no composition with the previous
+    parameters, no re-centring of the average); the loop stops after a pass
+    in which at most ``max_changed_frac * N`` particles changed any
+    parameter (shift, angle or mirror) since the pass before, or after
+    ``max_iter`` passes.  Returns (params of the last pass, average after it
+    [L, L] float32, passes run, changed fraction of passes 2, 3, ...).
+    """
+    parts = np.asarray(parts)
+    N = parts.shape[0]
+    if init is None:
+        Y = parts.astype(np.float64).mean(axis=0).astype(np.float32)[None]
+    else:
+        Y = np.asarray(init, dtype=np.float32).reshape(1, g.L, g.L)
+    prev = None
+    fracs = []
+    params, it = None, 0
+    for it in range(1, max_iter + 1):
+        params = align(parts, Y, g)
+        Y = averages(parts, params, Y, g)[0].astype(np.float32)
+        if prev is not None:
+            n_changed = int(np.count_nonzero(params["flat_index"] != prev))
+            fracs.append(n_changed / N)
+            if n_changed <= max_changed_frac * N:
+                break
+        prev = params["flat_index"].copy()
+    return params, Y[0], it, fracs
