@@ -136,6 +136,9 @@ int mra_refset_info(mra_ctx* ctx, int32_t refset_id, int32_t* K, mra_geom* g);
  * reduction of Fig. 2): for every particle, every shift, both mirrors and
  * every reference, the CC over all n_phi angles, then the arg-max.  `parts`
  * is float32 [N][L][L]; `out` arrays have length N.  N = 0 is a no-op.
+ * A refset with one reference (K = 1) runs a fused kernel (resampling, ring
+ * FFTs, correlation, inverse FFT, arg-max and cc2 in one launch, FP32 for
+ * every precision, no workspace): the single-reference pass of RFA.
  * Errors: MRA_E_NOREF, MRA_E_INVAL, MRA_E_NOMEM. */
 int mra_align(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
               mra_result* out);
@@ -175,6 +178,25 @@ int mra_update_averages(mra_ctx* ctx, int32_t refset_id, const float* parts, int
 int mra_classify(mra_ctx* ctx, int32_t refset_id, const mra_geom* g, const float* parts, int64_t N,
                  float* averages, int32_t K, int32_t max_iter, double max_changed_frac,
                  mra_result* out, int32_t* counts, int32_t* n_iter, int64_t* changed);
+
+/* Reference-free alignment (RFA; the GPU ISAC routine that Sec. 2 builds
+ * the MRA on and Sec. 5 benchmarks): the iterative loop of mra_classify
+ * with one running average as the only reference.  With start_from_mean = 1
+ * `average` is first set to the plain mean of the N particles; otherwise it
+ * is the starting reference.  Pass i aligns every particle against
+ * `average` (all shifts, both mirrors if g->mirror, all angles; the
+ * fused K = 1 kernel) and rebuilds it from the aligned particles.  The
+ * paper gives no stop rule; this one stops after pass i >= 2 when at most
+ * max_changed_frac * N particles changed any parameter (shift, angle,
+ * mirror) since pass i - 1, or after max_iter passes.
+ *  average  float32 [L][L] device, in/out
+ *  out      the last pass's parameters (ref = 0); cc2 costs nothing extra
+ *  n_iter, changed  as in mra_classify (changed[0] = N)
+ * The refset id is loaded with K = 1 and geometry g on every pass.
+ * Errors as mra_classify. */
+int mra_rfa(mra_ctx* ctx, int32_t refset_id, const mra_geom* g, const float* parts, int64_t N,
+            float* average, int32_t start_from_mean, int32_t max_iter, double max_changed_frac,
+            mra_result* out, int32_t* n_iter, int64_t* changed);
 
 /* Alignment of several stacks of uneven size (each against its own refset,
  * with its own shift range) in one call.  Stacks are cut into pieces that
@@ -218,8 +240,8 @@ int mra_debug_refs(mra_ctx* ctx, int32_t refset_id, float* qhat, double* norm);
 
 /* Kernel timing for measurement.  mra_profile(ctx, 1) clears and starts
  * recording a HIP event pair around every launch of the named kernel groups
- * ("polar", "corr", "merge", "rescore", "maxabs", "averages", and "corr2" for
- * the runner-up pass of cc2) on the context's stream;
+ * ("polar", "corr", "merge", "rescore", "maxabs", "averages", "corr2" for
+ * the runner-up pass of cc2, and "rfa" for the fused K = 1 kernel) on the context's stream;
  * mra_profile(ctx, 0) stops.  mra_profile_read synchronises the stream and
  * returns the summed device time and the launch count of one group. */
 int mra_profile(mra_ctx* ctx, int enable);

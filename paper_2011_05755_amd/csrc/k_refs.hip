@@ -7,7 +7,8 @@
 //   FP32  [ref tile][slot][t < R4][64], lane = g*16 + q*8 + ref%8, ring = g*R4 + t
 //   16-bit [ref tile][slot][s < NS][64][8], ring = g*R4 + 8 s + e
 // with q = 0 -> c - d and q = 1 -> c + d for c + id = Q_f (slot f = 1..127)
-// and c = Q_0, d = Q_128 in slot 0.
+// and c = Q_0, d = Q_128 in slot 0; with one reference also
+//   single [ring][slot] (c - d, c + d) for the fused single-reference kernel.
 #include "mra_common.h"
 
 namespace mra {
@@ -133,6 +134,23 @@ __global__ void k_ref_pack16(RefArgs a) {
   }
 }
 
+// K = 1: the single reference's weighted spectrum per (ring, slot) as
+// (c - d, c + d), read by the fused single-reference kernel.
+__global__ void k_ref_pack_single(RefArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.R * kSlots) return;
+  const int ring = i / kSlots, slot = i % kSlots;
+  double c, d;
+  if (slot == 0) {
+    c = a.Qs[0 * a.R + ring].x;
+    d = a.Qs[128 * a.R + ring].x;
+  } else {
+    c = a.Qs[slot * a.R + ring].x;
+    d = a.Qs[slot * a.R + ring].y;
+  }
+  a.G1[i] = make_float2((float)(c - d), (float)(c + d));
+}
+
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_ref_stage1(const RefArgs& a, hipStream_t st) {
@@ -148,6 +166,7 @@ hipError_t launch_ref_stage1(const RefArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_ref_stage2(const RefArgs& a, hipStream_t st) {
+  if (a.G1) hipLaunchKernelGGL(k_ref_pack_single, dim3(blocks_for((int64_t)a.R * kSlots, 256)), dim3(256), 0, st, a);
   if (a.prec == kFP32) {
     const int64_t n = (int64_t)a.n_ref_tiles * kSlots * a.R4 * 64;
     hipLaunchKernelGGL(k_ref_pack32, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);

@@ -29,6 +29,7 @@ struct Refset {
   int K = 0, R = 0, R4 = 0, NS = 0, n_kt = 0;
   float* B32 = nullptr;
   uint16_t* B16 = nullptr;
+  float2* G1 = nullptr;    // K = 1: spectrum table of the fused single-reference kernel
   float* qhat = nullptr;
   double* norm = nullptr;
   Stencil* stencil = nullptr;
@@ -125,7 +126,7 @@ void clear_profile(mra_ctx* c) {
 }
 
 void free_refset(Refset& r) {
-  for (void* p : {(void*)r.B32, (void*)r.B16, (void*)r.qhat, (void*)r.norm, (void*)r.stencil})
+  for (void* p : {(void*)r.B32, (void*)r.B16, (void*)r.G1, (void*)r.qhat, (void*)r.norm, (void*)r.stencil})
     if (p) (void)hipFree(p);
   r = Refset{};
 }
@@ -296,6 +297,28 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   }
 }
 
+// One reference (K = 1): the fused single-reference kernel over the whole
+// stack; it needs no workspace.
+void run_single(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, int64_t N, const mra_result* out) {
+  const int L = rs.g.L;
+  const int64_t step = INT32_MAX / 2;
+  for (int64_t n0 = 0; n0 < N; n0 += step) {
+    RfaArgs ra{};
+    ra.parts = parts + (size_t)n0 * L * L;
+    ra.n_part = (int)std::min<int64_t>(step, N - n0);
+    ra.out_off = n0;
+    ra.L = L; ra.R = rs.R; ra.T = p.T; ra.S1 = p.S1; ra.S = p.S; ra.M = p.M;
+    ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx;
+    ra.stencil = rs.stencil;
+    ra.cs32 = c->cs32;
+    ra.G = rs.G1;
+    ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
+    ra.psi = out->psi; ra.mirror = out->mirror; ra.flat = out->flat_index;
+    ra.cc = out->cc; ra.cc2 = out->cc2;
+    timed(c, "rfa", [&] { hip_check(c, launch_rfa(ra, c->stream), "rfa"); });
+  }
+}
+
 void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, const mra_result* out,
                 float* table) {
   Refset& rs = get_refset(c, id);
@@ -304,6 +327,10 @@ void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, co
   if (!parts) throw Fail{MRA_E_INVAL, "parts is NULL"};
   if (!table) check_result(out);
   const Plan p = plan_for(rs, T < 0 ? rs.g.shift_max : T);
+  if (rs.K == 1 && !table) {
+    run_single(c, rs, p, parts, N, out);
+    return;
+  }
   const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
   for (int64_t n0 = 0; n0 < N; n0 += step) {
     const int nc = (int)std::min<int64_t>(step, N - n0);
@@ -432,6 +459,10 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
     if (s.N <= 0) continue;
     const Refset& rs = get_refset(c, s.refset_id);
     const Plan& p = plans[i];
+    if (rs.K == 1) {  // one reference: the fused single-reference kernel
+      run_single(c, rs, p, s.parts, s.N, &s.out);
+      continue;
+    }
     if (s.out.cc2) {  // runner-up requested: the per-chunk path, which runs the second pass
       const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
       for (int64_t n0 = 0; n0 < s.N; n0 += step)
@@ -528,6 +559,8 @@ void load_refs_impl(mra_ctx* c, int32_t id, const float* refs, int32_t K, const 
       rs.B16 = (uint16_t*)alloc(c, (size_t)rs.n_kt * kSlots * rs.NS * 64 * 8 * sizeof(uint16_t), "B16");
     ra.B32 = rs.B32;
     ra.B16 = rs.B16;
+    if (K == 1) rs.G1 = (float2*)alloc(c, (size_t)rs.R * kSlots * sizeof(float2), "G1");
+    ra.G1 = rs.G1;
     hip_check(c, launch_ref_stage2(ra, st), "ref stage 2");
   } catch (...) {
     free_refset(rs);
@@ -542,16 +575,14 @@ void load_refs_impl(mra_ctx* c, int32_t id, const float* refs, int32_t K, const 
   c->refs[id] = rs;
 }
 
-void update_averages_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, const mra_result* params,
-                          float* averages, int32_t* counts) {
-  Refset& rs = get_refset(c, id);
+void averages_core(mra_ctx* c, int K, int L, const float* parts, int64_t N, const mra_result* params,
+                   float* averages, int32_t* counts) {
   if (N < 0 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
   if (!averages || !counts) throw Fail{MRA_E_INVAL, "averages and counts must be non-NULL"};
   if (!params || !params->ref || !params->shift_x || !params->shift_y || !params->psi || !params->mirror)
     throw Fail{MRA_E_INVAL, "params arrays must be non-NULL"};
   if (N > 0 && !parts) throw Fail{MRA_E_INVAL, "parts is NULL"};
   hipStream_t st = c->stream;
-  const int K = rs.K, L = rs.g.L;
   if (N == 0) {
     hip_check(c, hipMemsetAsync(counts, 0, K * sizeof(int32_t), st), "memset");
     return;
@@ -574,6 +605,70 @@ void update_averages_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N,
   a.averages = averages;
   a.counts = counts;
   timed(c, "averages", [&] { hip_check(c, launch_averages(a, st), "averages"); });
+}
+
+void update_averages_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, const mra_result* params,
+                          float* averages, int32_t* counts) {
+  const Refset& rs = get_refset(c, id);
+  averages_core(c, rs.K, rs.g.L, parts, N, params, averages, counts);
+}
+
+// The outer repeat: load the averages as references, align, count the
+// particles whose key (class, or with by_flat the whole parameter set)
+// changed since the previous pass, update the averages.
+void iterate_impl(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts, int64_t N, float* averages,
+                  int32_t K, int32_t max_iter, double max_changed_frac, const mra_result* out, int32_t* counts,
+                  int32_t* n_iter, int64_t* changed, bool by_flat) {
+  // a tuning set on this refset id carries over when the geometry matches
+  int variant = -1, chunk = 0;
+  auto old = c->refs.find(id);
+  if (old != c->refs.end() && old->second.K == K && std::memcmp(&old->second.g, g, sizeof(mra_geom)) == 0) {
+    variant = old->second.variant;
+    chunk = old->second.chunk;
+  }
+  hipStream_t st = c->stream;
+  mra_result o = *out;
+  if (by_flat && !o.flat_index) o.flat_index = (int32_t*)ws_get(c, "iter_flat", (size_t)N * sizeof(int32_t));
+  const int32_t* key = by_flat ? o.flat_index : o.ref;
+  int32_t* prev = (int32_t*)ws_get(c, "iter_prev", (size_t)N * sizeof(int32_t));
+  int* cnt = (int*)ws_get(c, "iter_count", 256);
+  *n_iter = 0;
+  for (int it = 1; it <= max_iter; ++it) {
+    load_refs_impl(c, id, averages, K, g);
+    if (variant >= 0) {
+      Refset& rs = c->refs[id];
+      rs.variant = variant;
+      rs.chunk = chunk;
+    }
+    align_impl(c, id, parts, N, -1, &o, nullptr);
+    int64_t n_changed = N;
+    if (it == 1) {
+      hip_check(c, hipMemcpyAsync(prev, key, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, st), "memcpy");
+    } else {
+      int h = 0;
+      hip_check(c, hipMemsetAsync(cnt, 0, sizeof(int), st), "memset");
+      hip_check(c, launch_count_changed(key, prev, (int)N, cnt, st), "count changed");
+      hip_check(c, hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, st), "memcpy");
+      hip_check(c, hipStreamSynchronize(st), "sync");
+      n_changed = h;
+    }
+    update_averages_impl(c, id, parts, N, &o, averages, counts);
+    if (changed) changed[it - 1] = n_changed;
+    *n_iter = it;
+    if (it > 1 && (double)n_changed <= max_changed_frac * (double)N) break;
+  }
+  hip_check(c, hipStreamSynchronize(st), "sync");
+}
+
+void check_loop_args(const mra_geom* g, const float* parts, int64_t N, const float* averages, int32_t max_iter,
+                     double max_changed_frac, const mra_result* out, const int32_t* n_iter) {
+  check_geom(g);
+  if (N < 1 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
+  if (!parts || !averages || !n_iter) throw Fail{MRA_E_INVAL, "NULL argument"};
+  if (max_iter < 1) throw Fail{MRA_E_INVAL, "max_iter must be >= 1"};
+  if (!(max_changed_frac >= 0.0 && max_changed_frac <= 1.0))
+    throw Fail{MRA_E_INVAL, "max_changed_frac must lie in [0, 1]"};
+  check_result(out);
 }
 
 template <class F>
@@ -710,51 +805,26 @@ int mra_classify(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts, 
                  int32_t K, int32_t max_iter, double max_changed_frac, mra_result* out, int32_t* counts,
                  int32_t* n_iter, int64_t* changed) {
   return guard(c, [&] {
-    check_geom(g);
+    check_loop_args(g, parts, N, averages, max_iter, max_changed_frac, out, n_iter);
     if (K < 1) throw Fail{MRA_E_INVAL, "K must be >= 1"};
-    if (N < 1 || N > (int64_t)INT32_MAX / 2) throw Fail{MRA_E_INVAL, "N out of range"};
-    if (!parts || !averages || !counts || !n_iter) throw Fail{MRA_E_INVAL, "NULL argument"};
-    if (max_iter < 1) throw Fail{MRA_E_INVAL, "max_iter must be >= 1"};
-    if (!(max_changed_frac >= 0.0 && max_changed_frac <= 1.0))
-      throw Fail{MRA_E_INVAL, "max_changed_frac must lie in [0, 1]"};
-    check_result(out);
-    // a tuning set on this refset id carries over when the geometry matches
-    int variant = -1, chunk = 0;
-    auto old = c->refs.find(id);
-    if (old != c->refs.end() && old->second.K == K && std::memcmp(&old->second.g, g, sizeof(mra_geom)) == 0) {
-      variant = old->second.variant;
-      chunk = old->second.chunk;
+    if (!counts) throw Fail{MRA_E_INVAL, "counts is NULL"};
+    iterate_impl(c, id, g, parts, N, averages, K, max_iter, max_changed_frac, out, counts, n_iter, changed, false);
+  });
+}
+
+int mra_rfa(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts, int64_t N, float* average,
+            int32_t start_from_mean, int32_t max_iter, double max_changed_frac, mra_result* out, int32_t* n_iter,
+            int64_t* changed) {
+  return guard(c, [&] {
+    check_loop_args(g, parts, N, average, max_iter, max_changed_frac, out, n_iter);
+    int32_t* cnt = (int32_t*)ws_get(c, "rfa_count", 256);
+    if (start_from_mean) {  // the plain mean: the average update with every parameter zero
+      hipStream_t st = c->stream;
+      for (int32_t* p : {out->ref, out->shift_x, out->shift_y, out->psi, out->mirror})
+        hip_check(c, hipMemsetAsync(p, 0, (size_t)N * sizeof(int32_t), st), "memset");
+      averages_core(c, 1, g->L, parts, N, out, average, cnt);
     }
-    hipStream_t st = c->stream;
-    int32_t* prev = (int32_t*)ws_get(c, "cls_prev", (size_t)N * sizeof(int32_t));
-    int* cnt = (int*)ws_get(c, "cls_count", 256);
-    *n_iter = 0;
-    for (int it = 1; it <= max_iter; ++it) {
-      load_refs_impl(c, id, averages, K, g);
-      if (variant >= 0) {
-        Refset& rs = c->refs[id];
-        rs.variant = variant;
-        rs.chunk = chunk;
-      }
-      align_impl(c, id, parts, N, -1, out, nullptr);
-      int64_t n_changed = N;
-      if (it == 1) {
-        hip_check(c, hipMemcpyAsync(prev, out->ref, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, st),
-                  "memcpy");
-      } else {
-        int h = 0;
-        hip_check(c, hipMemsetAsync(cnt, 0, sizeof(int), st), "memset");
-        hip_check(c, launch_count_changed(out->ref, prev, (int)N, cnt, st), "count changed");
-        hip_check(c, hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, st), "memcpy");
-        hip_check(c, hipStreamSynchronize(st), "sync");
-        n_changed = h;
-      }
-      update_averages_impl(c, id, parts, N, out, averages, counts);
-      if (changed) changed[it - 1] = n_changed;
-      *n_iter = it;
-      if (it > 1 && (double)n_changed <= max_changed_frac * (double)N) break;
-    }
-    hip_check(c, hipStreamSynchronize(st), "sync");
+    iterate_impl(c, id, g, parts, N, average, 1, max_iter, max_changed_frac, out, cnt, n_iter, changed, true);
   });
 }
 

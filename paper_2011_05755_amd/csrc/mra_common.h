@@ -109,6 +109,20 @@ struct RescoreBatch {
   RescoreArgs piece[kMaxBatchPieces];
 };
 
+// Alignment against one reference (K = 1): resampling, ring FFTs,
+// correlation, inverse FFT and arg-max fused per particle.
+struct RfaArgs {
+  const float* parts;    // first particle of the call, [n][L][L]
+  int n_part;
+  int64_t out_off;
+  int L, R, T, S1, S, M, Lp, pad, cx;
+  const Stencil* stencil;
+  const float2* cs32;
+  const float2* G;       // [R][128]: (c - d, c + d) of the reference's weighted spectrum per slot
+  int32_t *ref, *shift_x, *shift_y, *psi, *mirror, *flat;
+  float *cc, *cc2;
+};
+
 // ---- launchers (one .hip file each) ----
 hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st);
 size_t polar_lds_bytes(int Lp);
@@ -123,6 +137,7 @@ hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st);
 hipError_t launch_merge_batch(const MergeBatch& b, hipStream_t st);
 hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st);
 hipError_t launch_part_maxabs(const float* x, int n_part, int L, float* out, hipStream_t st);
+hipError_t launch_rfa(const RfaArgs& a, hipStream_t st);
 // count[0] += #{i : cls[i] != prev[i]}; then prev = cls
 hipError_t launch_count_changed(const int32_t* cls, int32_t* prev, int n, int* count, hipStream_t st);
 
@@ -138,6 +153,7 @@ struct RefArgs {
   float* qhat32;     // [K][R][256]
   float* B32;
   uint16_t* B16;
+  float2* G1;        // K = 1: [R][128] (c - d, c + d) per slot, else null
   float* bmax;       // device scalar: max |B| (for the FP16 scale)
   float b_scale;
 };

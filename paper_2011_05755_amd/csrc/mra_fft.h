@@ -179,6 +179,17 @@ MRA_HD void fwd_emit(int l, const float2 (&Za)[8], const float2 (&Zb)[8], W w256
   }
 }
 
+// The slots fwd_emit hands lane l, in emission order (they depend on l only).
+MRA_HD void emit_slots(int l, int (&sl)[16]) {
+  const bool z = l == 0;
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) {
+    const int f = k2 == 0 ? l : (z ? (k2 < 4 ? 16 * k2 : 16 * k2 - 56) : l + 16 * k2);
+    sl[2 * k2] = f;
+    sl[2 * k2 + 1] = (k2 == 0 && z) ? 64 : 128 - f;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Inverse transform over angle of the correlation spectra of one
 // (row, reference) pair, both mirrors at once.

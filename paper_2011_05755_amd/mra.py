@@ -21,7 +21,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 
 EXPORTS = (
     "mra_create", "mra_destroy", "mra_load_refs", "mra_unload_refs", "mra_refset_info",
-    "mra_align", "mra_update_averages", "mra_classify", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
+    "mra_align", "mra_update_averages", "mra_classify", "mra_rfa", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
     "mra_debug_polar",
     "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_profile", "mra_profile_read",
     "mra_last_error", "mra_strerror",
@@ -76,6 +76,8 @@ def load_library() -> ctypes.CDLL:
         "mra_update_averages": [vp, i32, vp, i64, ctypes.POINTER(Result), vp, vp],
         "mra_classify": [vp, i32, ctypes.POINTER(Geom), vp, i64, vp, i32, i32, ctypes.c_double,
                          ctypes.POINTER(Result), vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
+        "mra_rfa": [vp, i32, ctypes.POINTER(Geom), vp, i64, vp, i32, i32, ctypes.c_double, ctypes.POINTER(Result),
+                    ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "mra_align_batch": [vp, ctypes.POINTER(Stack), i32],
         "mra_set_tuning": [vp, i32, ctypes.POINTER(Tuning)],
         "mra_get_tuning": [vp, i32, ctypes.POINTER(Tuning)],
@@ -272,6 +274,35 @@ class Context:
         self.refsets[refset_id] = Refset(refset_id, K, L, r_min, r_max, n_phi, shift_max, int(mirror), precision,
                                          int(normalize))
         return out, counts, n_iter.value, list(changed[:n_iter.value])
+
+    def rfa(self, refset_id: int, parts: torch.Tensor, r_min: int, r_max: int, shift_max: int,
+            average: torch.Tensor | None = None, max_iter: int = 10, max_changed_frac: float = 0.0,
+            n_phi: int = 256, mirror: bool = True, normalize: bool = True, out: AlignResult | None = None,
+            with_cc2: bool = True):
+        """Reference-free alignment (mra_rfa).  average [L, L]: the starting
+        reference, updated in place; None starts from the plain mean.
+        Returns (params of the last pass, average, passes run, changed-per-pass list)."""
+        L = parts.shape[-1]
+        _check_images(parts, L, "parts")
+        N = parts.shape[0]
+        start_from_mean = average is None
+        if average is None:
+            average = torch.empty((L, L), dtype=torch.float32, device=parts.device)
+        if not (average.is_cuda and average.dtype == torch.float32 and tuple(average.shape) == (L, L)
+                and average.is_contiguous()):
+            raise ValueError(f"average must be a contiguous float32 CUDA tensor [{L}, {L}]")
+        if out is None:
+            out = AlignResult.empty(N, parts.device, with_cc2=with_cc2)
+        g = Geom(L, r_min, r_max, n_phi, shift_max, int(mirror), 0, int(normalize))
+        res = out.c_struct()
+        n_iter = ctypes.c_int32()
+        changed = (ctypes.c_int64 * max(1, max_iter))()
+        self._check(self.lib.mra_rfa(self._h, refset_id, ctypes.byref(g), _ptr(parts), N, _ptr(average),
+                                     int(start_from_mean), max_iter, max_changed_frac, ctypes.byref(res),
+                                     ctypes.byref(n_iter), changed))
+        self.refsets[refset_id] = Refset(refset_id, 1, L, r_min, r_max, n_phi, shift_max, int(mirror), "fp32",
+                                         int(normalize))
+        return out, average, n_iter.value, list(changed[:n_iter.value])
 
     # ---- tile configuration (see include/mra.h, mra_tuning) ----
     def set_tuning(self, refset_id: int, corr_variant: int = -1, chunk_particles: int = 0):

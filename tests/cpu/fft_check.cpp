@@ -81,7 +81,11 @@ int main() {
       for (int n2 = 0; n2 < 8; ++n2) { Za[n2] = Y[n2][k1a]; Zb[n2] = Y[n2][k1b]; }
       mra::dft8<-1>(Za);
       mra::dft8<-1>(Zb);
+      int order[16], e = 0;
+      mra::emit_slots(l, order);
       mra::fwd_emit(l, Za, Zb, tw256, [&](int slot, float a, float b) {
+        check(e < 16 && order[e] == slot, "emit_slots order", e);
+        ++e;
         if (slot == 0) {
           seen[0]++; seen[128]++;
           err = std::fmax(err, std::fabs(a - P[0].real()));
