@@ -218,10 +218,16 @@ int mra_align_batch(mra_ctx* ctx, const mra_stack* stacks, int32_t n);
  *                cannot serve the geometry.
  *  chunk_particles  particles per chunk (0: derived from the workspace cap);
  *                also caps the pieces mra_align_batch cuts the refset's stacks into.
+ *  prune         -1 or 1: skip the inverse FFT over angle of every (particle
+ *                row, reference) pair whose upper bound on the CC (from its
+ *                spectrum: exact magnitudes of the 32 lowest frequency slots,
+ *                Cauchy-Schwarz over the energy of the rest) lies below the
+ *                row's best so far, so it cannot win; 0: evaluate every pair.
  * Results do not depend on the tuning (bit for bit). */
 typedef struct mra_tuning {
   int32_t corr_variant;
   int32_t chunk_particles;
+  int32_t prune;
 } mra_tuning;
 int mra_set_tuning(mra_ctx* ctx, int32_t refset_id, const mra_tuning* t);
 int mra_get_tuning(mra_ctx* ctx, int32_t refset_id, mra_tuning* t);

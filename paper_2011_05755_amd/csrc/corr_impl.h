@@ -100,6 +100,10 @@ __device__ __forceinline__ float a_elem(const CorrArgs& a, const float* ap, int 
   return __uint_as_float(__float_as_uint(x) & keep);
 }
 
+// Frequency slots below kLowSlots enter the pruning bound with their exact
+// magnitudes, the others through their summed energy.
+constexpr int kLowSlots = 32;
+
 // store a 16x16 MFMA block of slot `slot` into the LDS spectrum state
 __device__ __forceinline__ void store_block(float* st, int slot, int ln, f32x4 acc) {
   const int p = ln >> 5, q = (ln >> 3) & 1, ref = ln & 7, row0 = ((ln >> 4) & 1) * 4;
@@ -108,6 +112,14 @@ __device__ __forceinline__ void store_block(float* st, int slot, int ln, f32x4 a
     const int P = (row0 + i2) * 8 + ref;
     st[((slot * 2 + p) * 64 + P) * 2 + (q ^ p)] = acc[i2];
   }
+}
+
+// Add the squares of the lane's block entries, times msk (1 for a slot at or
+// above kLowSlots, else 0), to e: its four rows' share of the pairs'
+// high-slot energy.  Slot w + NW i is a high slot exactly when i >= kLowSlots / NW.
+__device__ __forceinline__ void add_energy(float (&e)[4], f32x4 acc, float msk) {
+#pragma unroll
+  for (int i2 = 0; i2 < 4; ++i2) e[i2] = fmaf(acc[i2] * msk, acc[i2], e[i2]);
 }
 
 // Contraction of one reference tile with FP32 operands for the wave's
@@ -121,6 +133,7 @@ struct Fp32Contract {
   static constexpr int SPW = kSlots / NW;
   static constexpr int RX = EXACT ? MAXR : 0;
   float areg[RES ? SPW : 1][RES ? MAXR : 1];
+  float e[4];  // high-slot energy of the lane's entries (store_block)
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
@@ -135,6 +148,7 @@ struct Fp32Contract {
 
   __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
     const int R4 = EXACT ? MAXR : a.R4;
+    e[0] = e[1] = e[2] = e[3] = 0.f;
     auto loadb = [&](int i, float (&dst)[MAXR]) {
       const float* bp = a.B32 + ((size_t)(kt * kSlots + w + NW * i) * R4) * 64 + ln;
 #pragma unroll
@@ -160,6 +174,10 @@ struct Fp32Contract {
         if (i + 3 < SPW) loadb(i + 3, b[(i + 3) % 4]);
         store_block(st, w + NW * i, ln, acc0);
         store_block(st, w + NW * (i + 1), ln, acc1);
+        if (i >= kLowSlots / NW) {
+          add_energy(e, acc0, 1.f);
+          add_energy(e, acc1, 1.f);
+        }
       }
     } else {
       // both operands streamed, one slot ahead (explicit double buffer so
@@ -176,6 +194,7 @@ struct Fp32Contract {
         for (int t = 0; t < MAXR; ++t)
           if (t < R4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t], y[t], acc, 0, 0, 0);
         store_block(st, slot, ln, acc);
+        add_energy(e, acc, slot >= kLowSlots ? 1.f : 0.f);
       };
       loadb(0, b0);
       loada(0, a0);
@@ -206,6 +225,7 @@ struct Half16Contract {
   typedef typename Op16<PREC>::T V;
   u32x4 areg[RES ? SPW : 1][NS];
   float scale_ = 1.f;
+  float e[4];  // high-slot energy of the lane's entries (store_block)
 
   __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, float (&v)[8 * NS], bool nt) {
     const float* ap = a_lane(a, tile, slot, ln);
@@ -239,6 +259,7 @@ struct Half16Contract {
   __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
     const uint4* B = reinterpret_cast<const uint4*>(a.B16);
     const int ns = EXACT ? NS : a.NS;
+    e[0] = e[1] = e[2] = e[3] = 0.f;
     auto loadb = [&](int i, uint4 (&dst)[NS]) {
       const uint4* bp = B + ((size_t)(kt * kSlots + w + NW * i) * ns) * 64 + ln;
 #pragma unroll
@@ -250,6 +271,7 @@ struct Half16Contract {
       for (int s = 0; s < NS; ++s)
         if (s < ns) acc = Op16<PREC>::mfma(__builtin_bit_cast(V, x[s]), __builtin_bit_cast(V, y[s]), acc);
       store_block(st, slot, ln, acc);
+      return acc;
     };
     if constexpr (RES) {
       uint4 b[2][NS];
@@ -257,7 +279,11 @@ struct Half16Contract {
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
         if (i + 1 < SPW) loadb(i + 1, b[(i + 1) % 2]);
-        chain(areg[RES ? i : 0], b[i % 2], w + NW * i);
+        const f32x4 acc = chain(areg[RES ? i : 0], b[i % 2], w + NW * i);
+        if (i >= kLowSlots / NW) add_energy(e, acc, 1.f);
+        // keep each slot's store next to its products (a schedule that
+        // defers them all holds 16 blocks of results and runs slower)
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       // explicit double buffer so that the slot loop need not be unrolled
@@ -271,13 +297,13 @@ struct Half16Contract {
         loadb(i + 1, b1);
         fetch(a, tile, w + NW * (i + 1), ln, r1, false);
         pack(r0, x);
-        chain(x, b0, w + NW * i);
+        add_energy(e, chain(x, b0, w + NW * i), i >= kLowSlots / NW ? 1.f : 0.f);
         if (i + 2 < SPW) {
           loadb(i + 2, b0);
           fetch(a, tile, w + NW * (i + 2), ln, r0, false);
         }
         pack(r1, x);
-        chain(x, b1, w + NW * (i + 1));
+        add_energy(e, chain(x, b1, w + NW * (i + 1)), i + 1 >= kLowSlots / NW ? 1.f : 0.f);
       }
     }
   }
@@ -287,8 +313,11 @@ template <int NW>
 struct CorrSmem {
   float* st;        // [128][2][64][2] spectra of the 64 (row, ref) pairs
   float2* stc;
-  float* cand_v;    // [NW][64]
+  float* cand_v;    // [16][64]: per (wave, pass-2 row of the wave) and pair
   int* cand_i;
+  float* pe;        // [NW][2][64] high-slot energy of each pair, per wave and p half
+  float2* pb;       // [NW][64] low-slot bound of each pair (both mirrors), per wave
+  int* list;        // [NW][64] each wave's list of the pairs that need the inverse FFT
   float* rb_v;      // [8] running best per row
   int* rb_i;
   float2* tw;       // exp(-2 pi i e / 256)
@@ -297,17 +326,46 @@ struct CorrSmem {
     st = smem;
     stc = reinterpret_cast<float2*>(smem);
     cand_v = smem + kSlots * 2 * 64 * 2;
-    cand_i = reinterpret_cast<int*>(cand_v + NW * 64);
-    rb_v = reinterpret_cast<float*>(cand_i + NW * 64);
+    cand_i = reinterpret_cast<int*>(cand_v + 16 * 64);
+    pe = reinterpret_cast<float*>(cand_i + 16 * 64);
+    pb = reinterpret_cast<float2*>(pe + 2 * NW * 64);
+    list = reinterpret_cast<int*>(pb + NW * 64);
+    rb_v = reinterpret_cast<float*>(list + NW * 64);
     rb_i = reinterpret_cast<int*>(rb_v + 8);
     tw = reinterpret_cast<float2*>(rb_i + 8);
     item = reinterpret_cast<int*>(tw + kNphi);
   }
   static constexpr size_t bytes() {
-    return (size_t)kSlots * 2 * 64 * 2 * sizeof(float) + 2 * NW * 64 * sizeof(float) + 16 * sizeof(float) +
-           kNphi * sizeof(float2) + 4 * sizeof(int);
+    return (size_t)kSlots * 2 * 64 * 2 * sizeof(float) + 2 * 16 * 64 * sizeof(float) +
+           5 * NW * 64 * sizeof(float) + 16 * sizeof(float) + kNphi * sizeof(float2) + 4 * sizeof(int);
   }
 };
+
+// rotate within rows of 16 lanes (DPP row_ror): lane i gets lane (i + O) mod 16's value
+template <int O>
+__device__ __forceinline__ int ror16(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + O, 0xf, 0xf, false);
+}
+template <int O>
+__device__ __forceinline__ float ror16f(float v) {
+  return __int_as_float(ror16<O>(__float_as_int(v)));
+}
+// (v, i) := the better of itself and the lane O further on in its row of 16
+template <int O>
+__device__ __forceinline__ void better_ror(float& v, int& i) {
+  const float v2 = ror16f<O>(v);
+  const int i2 = ror16<O>(i);
+  if (better(v2, i2, v, i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Power-of-two FP16 scale of chunk row r: |a +- b| <= 2 * 256 * max|pixel|
 // of the row's particle is mapped below 2^14.
@@ -322,8 +380,23 @@ __device__ __forceinline__ float fp16_scale(const CorrArgs& a, int r) {
 constexpr int kArgmax = 0, kTable = 1, kRunnerUp = 2;
 
 // One 8-row tile against every reference tile (see the file comment).
+//
+// Exact pruning (a.prune, not in table mode): after the contraction of a
+// reference tile, every (row, ref) pair gets an upper bound of its CC over
+// all angles, per mirror m,
+//   c_m[a] <= |g_0| + |g_128| + sum_{f=1}^{127} 2 |G_m,f|,
+// with the terms of slots below kLowSlots taken exactly from the spectra and
+// the rest bounded by Cauchy-Schwarz through the pairs' high-slot energy
+// (sum of 2|G_m,f| <= sqrt(2 * 96 * sum of the squared MFMA entries)).  A pair
+// whose bound, inflated by 2^-12 against rounding, is below the row's best
+// over earlier reference tiles cannot win (a tie with an earlier tile loses
+// on the flat index), so its inverse FFT and arg-max are skipped.  The live
+// pairs are packed into the lanes of each wave: a pass takes
+// ceil(CPW * live / 64) steps instead of CPW (CPW = 16 / NW columns or rows
+// per wave).  Results are identical with and without pruning.
 template <int PREC, int NW, class Contract, int MODE>
 __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const CorrSmem<NW>& sm, Contract& con) {
+  constexpr int CPW = 16 / NW;  // inverse-FFT columns (pass 1) and rows (pass 2) per wave
   const int tid = threadIdx.x, ln = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < 8) {
@@ -334,111 +407,230 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
   // particle (exact, so results do not depend on how particles are grouped)
   if constexpr (PREC == kFP32) con.load_a(a, tile, w, ln);
   else con.load_a(a, tile, w, ln, PREC == kFP16 ? fp16_scale(a, tile * kRowTile + (ln & 7)) : 1.f);
+  int* list = sm.list + w * 64;
+  const bool prune = MODE != kTable && a.prune;
 
   for (int kt = 0; kt < a.n_ref_tiles; ++kt) {
     // ---------------- contraction on the matrix cores ----------------
     con.run(a, sm.st, tile, kt, w, ln);
+    if (prune) {
+      // high-slot energy of each pair: the lane's four rows summed with its
+      // q partner (lane ^ 8, in the same row of 16: a DPP rotation by 8);
+      // the two p halves (lane ^ 32) are stored apart and added below
+      float e[4];
+#pragma unroll
+      for (int i2 = 0; i2 < 4; ++i2) e[i2] = con.e[i2] + ror16f<8>(con.e[i2]);
+      if ((ln & 8) == 0) {
+        const int ref = ln & 7, row0 = ((ln >> 4) & 1) * 4, p = ln >> 5;
+#pragma unroll
+        for (int i2 = 0; i2 < 4; ++i2) sm.pe[(w * 2 + p) * 64 + (row0 + i2) * 8 + ref] = e[i2];
+      }
+      // exact terms of the wave's own low slots (written by this wave)
+      lds_wave_sync();
+      const int P = ln;
+      float b0 = 0.f, b1 = 0.f;
+#pragma unroll
+      for (int i = 0; i < kLowSlots / NW; ++i) {
+        const int slot = w + NW * i;
+        const float2 h0 = sm.stc[(slot * 2) * 64 + P];      // (U00, U01)
+        const float2 h1 = sm.stc[(slot * 2 + 1) * 64 + P];  // (U11, U10)
+        const float s1 = h0.x + h1.x, d1 = h0.x - h1.x, s2 = h0.y + h1.y, d2 = h0.y - h1.y;
+        if (slot == 0) {  // |g_0| + |g_128|, the same for both mirrors
+          const float g = 0.25f * (fabsf(s1 + s2) + fabsf(s1 - s2));
+          b0 += g;
+          b1 += g;
+        } else {          // 2|G_0,f| = |(s1, d2)|, 2|G_1,f| = |(s2, d1)|
+          b0 += sqrtf(s1 * s1 + d2 * d2);
+          b1 += sqrtf(s2 * s2 + d1 * d1);
+        }
+      }
+      sm.pb[w * 64 + P] = make_float2(b0, b1);
+    }
     __syncthreads();
 
+    // ---------------- which pairs need the inverse FFT ----------------
+    uint64_t live = ~0ull;
+    if (prune) {
+      const int P = ln;
+      float B0 = 0.f, B1 = 0.f, E = 0.f;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) {
+        const float2 b = sm.pb[w2 * 64 + P];
+        B0 += b.x;
+        B1 += b.y;
+        E += sm.pe[(w2 * 2) * 64 + P] + sm.pe[(w2 * 2 + 1) * 64 + P];
+      }
+      const float bound = (a.M == 2 ? fmaxf(B0, B1) : B0) + sqrtf(2.f * (kSlots - kLowSlots) * E);
+      const int row_l = P >> 3, ref_l = P & 7;
+      const bool keep = tile * kRowTile + row_l < a.rows && kt * kRefTile + ref_l < a.K &&
+                        !(bound * (1.f + 1.f / 4096.f) < sm.rb_v[row_l]);
+      live = __ballot(keep);
+    }
+    const int n_live = __popcll(live);
+    {
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
+      if ((live >> ln) & 1) list[rank] = ln;
+      lds_wave_sync();
+    }
+    // The wave's inverse-FFT columns (pass 1) and rows (pass 2) are
+    // CPW * w + c, c = 0 .. CPW-1: lane group c (LPC lanes) takes column /
+    // row c for the live pairs list[n0 + ln % LPC].  Waves 0 .. NW/2-1 hold
+    // rows below 8 and the others rows from 8 on, so that every wave's
+    // pass-2 addresses share one shape (a lane base plus constant offsets).
+    constexpr int LPC = 64 / CPW;
+
     // ---------------- inverse FFT over angle, pass 1 ----------------
-    const int P = ln;
+    // H_j (j = 16 k1 + k2) of pair P: half 0 of slot j (j < 128) or half 1
+    // of slot 256 - j (j >= 128; slot 0 for j = 128)
+    {
 #pragma unroll 1
-    for (int c = 0; c < 16 / NW; ++c) {
-      const int k2 = w + NW * c;
-      float2 x[16];
+      for (int n0 = 0; n0 < n_live; n0 += LPC) {
+        // lane-derived values are recomputed here rather than kept live
+        // across the reference loop, where the registers hold the operand
+        int lnx = ln;
+        asm volatile("" : "+v"(lnx));
+        const int lane_n = lnx % LPC, k2 = CPW * w + lnx / LPC;
+        const bool act = n0 + lane_n < n_live;
+        const int P = list[act ? n0 + lane_n : 0];
+        const int lo = k2 * 128 + P, hi = P - k2 * 128;
+        const int mid = k2 == 0 ? 64 + P : hi + 257 * 64;
+        auto at = [&](int k1) { return k1 < 8 ? lo + k1 * 2048 : (k1 == 8 ? mid : hi + (513 - 32 * k1) * 64); };
+        float2 x[16];
 #pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) x[k1] = sm.stc[vidx(16 * k1 + k2, P)];
-      inv_pass1(k2, x, [&](int e) { return sm.tw[e & 255]; });
+        for (int k1 = 0; k1 < 16; ++k1) x[k1] = sm.stc[at(k1)];
+        inv_pass1(k2, x, [&](int e) { return sm.tw[e & 255]; });
+        if (act) {
 #pragma unroll
-      for (int n1 = 0; n1 < 16; ++n1) sm.stc[vidx(16 * n1 + k2, P)] = x[n1];
+          for (int n1 = 0; n1 < 16; ++n1) sm.stc[at(n1)] = x[n1];
+        }
+      }
     }
     __syncthreads();
 
     // ---------------- pass 2 + arg-max ----------------
-    const int row_l = P >> 3, ref_l = P & 7;
-    const int row = tile * kRowTile + row_l;
-    const int k = kt * kRefTile + ref_l;
-    // only values above the row's best of earlier reference tiles can win
-    // (a tie with an earlier tile loses: its flat index is smaller)
-    const float thr = sm.rb_v[row_l];
-    float bv = -INFINITY;
-    int bi = 0x7fffffff;
-    // the candidate left out of this pass (key m * 256 + angle of this
-    // lane's (row, ref)), or -1
-    int ex = -1;
-    if (MODE == kRunnerUp && row < a.rows && k < a.K) {
-      const int n = row / a.S, s = row - n * a.S;
-      const int e = a.excl[n];
-      if (e >= 0) {
-        const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
-        if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
-      }
-    }
+    {
+      const bool low = CPW * w < 8;  // wave-uniform
 #pragma unroll 1
-    for (int c = 0; c < 16 / NW; ++c) {
-      const int n1 = w + NW * c;
-      float2 x[16];
+      for (int n0 = 0; n0 < n_live; n0 += LPC) {
+        int lnx = ln;
+        asm volatile("" : "+v"(lnx));
+        const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
+        const bool act = n0 + lane_n < n_live;
+        const int P = list[act ? n0 + lane_n : 0];
+        const int row_l = P >> 3, ref_l = P & 7;
+        const int row = tile * kRowTile + row_l;
+        const int k = kt * kRefTile + ref_l;
+        float2 x[16];
+        if (low) {
+          const int base = n1 * 2048 + P;
 #pragma unroll
-      for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[vidx(16 * n1 + k2, P)];
-      inv_pass2(x);
-      if constexpr (MODE == kTable) {
-        if (row < a.rows && k < a.K) {
-          const int n = row / a.S, s = row - n * a.S;
-          const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
-          for (int m = 0; m < a.M; ++m) {
-            float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
+          for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
+        } else {
+          const int base = (513 - 32 * n1) * 64 + P;
+          x[0] = sm.stc[n1 == 8 ? 64 + P : base];
 #pragma unroll
-            for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
-          }
+          for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
         }
-      } else {
-        float mx = -INFINITY;
+        inv_pass2(x);
+        if constexpr (MODE == kTable) {
+          if (act && row < a.rows && k < a.K) {
+            const int n = row / a.S, s = row - n * a.S;
+            const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
+            for (int m = 0; m < a.M; ++m) {
+              float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
 #pragma unroll
-        for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
-        if (mx > thr && mx >= bv) {
-#pragma unroll
-          for (int n2 = 0; n2 < 16; ++n2) {
-            const int ang = n1 + 16 * n2;
-            if ((MODE != kRunnerUp || ang != ex) && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
-            if (a.M == 2 && (MODE != kRunnerUp || 256 + ang != ex) && better(x[n2].y, 256 + ang, bv, bi)) {
-              bv = x[n2].y;
-              bi = 256 + ang;
+              for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
             }
           }
+        } else {
+          // only values above the row's best of earlier reference tiles can
+          // win (a tie with an earlier tile loses: its flat index is smaller)
+          const float thr = sm.rb_v[row_l];
+          // the candidate left out of this pass (key m * 256 + angle of this
+          // lane's (row, ref)), or -1
+          int ex = -1;
+          if (MODE == kRunnerUp && row < a.rows && k < a.K) {
+            const int n = row / a.S, s = row - n * a.S;
+            const int e = a.excl[n];
+            if (e >= 0) {
+              const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
+              if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
+            }
+          }
+          float bv = -INFINITY;
+          int bi = 0x7fffffff;
+          float mx = -INFINITY;
+#pragma unroll
+          for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
+          if (MODE == kArgmax && mx > thr) {
+            // the lane's best is mx; its key is the smallest among the
+            // candidates equal to it (keys grow with n2, mirror 1 after 0)
+            bv = mx;
+            if (a.M == 2) {
+#pragma unroll
+              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
+            }
+#pragma unroll
+            for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
+          } else if (MODE == kRunnerUp && mx > thr) {
+#pragma unroll
+            for (int n2 = 0; n2 < 16; ++n2) {
+              const int ang = n1 + 16 * n2;
+              if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+              if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
+                bv = x[n2].y;
+                bi = 256 + ang;
+              }
+            }
+          }
+          if (act) {
+            sm.cand_v[(w * CPW + c) * 64 + P] = bv;
+            sm.cand_i[(w * CPW + c) * 64 + P] = bi;
+          }
         }
       }
-    }
-    if constexpr (MODE != kTable) {
-      sm.cand_v[w * 64 + P] = bv;
-      sm.cand_i[w * 64 + P] = bi;
     }
     __syncthreads();
     if constexpr (MODE != kTable) {
       // waves reduce the 8 rows: lane = (wave of origin, ref)
       for (int r = w; r < kRowTile; r += NW) {
+        if (((live >> (r * 8)) & 0xff) == 0) continue;  // no pair of the row can win
         const int ww = ln >> 3, ref = ln & 7;
+        const int P = r * 8 + ref;
         const int rr = tile * kRowTile + r;
         const int kk = kt * kRefTile + ref;
         float v = -INFINITY;
         int iota = 0x7fffffff;
-        for (int w2 = ww; w2 < NW; w2 += 8) {
-          const float v2 = sm.cand_v[w2 * 64 + r * 8 + ref];
-          const int li = sm.cand_i[w2 * 64 + r * 8 + ref];
-          if (li != 0x7fffffff && kk < a.K && rr < a.rows) {
-            const int m = li >> 8, ang = li & 255;
-            const int i2 = ((kk * a.M + m) * a.S + rr % a.S) * kNphi + ang;
-            if (better(v2, i2, v, iota)) { v = v2; iota = i2; }
+        if ((live >> P) & 1) {
+          for (int w2 = ww; w2 < NW; w2 += 8) {
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+              const float v2 = sm.cand_v[(w2 * CPW + c) * 64 + P];
+              const int li = sm.cand_i[(w2 * CPW + c) * 64 + P];
+              if (li != 0x7fffffff && kk < a.K && rr < a.rows) {
+                const int m = li >> 8, ang = li & 255;
+                const int i2 = ((kk * a.M + m) * a.S + rr % a.S) * kNphi + ang;
+                if (better(v2, i2, v, iota)) { v = v2; iota = i2; }
+              }
+            }
           }
         }
+        // best over each row of 16 lanes (DPP), then over the four rows
+        better_ror<8>(v, iota);
+        better_ror<4>(v, iota);
+        better_ror<2>(v, iota);
+        better_ror<1>(v, iota);
+        float bv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+        int bi = __builtin_amdgcn_readlane(iota, 0);
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const float v2 = __shfl_xor(v, o);
-          const int i2 = __shfl_xor(iota, o);
-          if (better(v2, i2, v, iota)) { v = v2; iota = i2; }
+        for (int l0 = 16; l0 < 64; l0 += 16) {
+          const float v2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l0));
+          const int i2 = __builtin_amdgcn_readlane(iota, l0);
+          if (better(v2, i2, bv, bi)) { bv = v2; bi = i2; }
         }
-        if (ln == 0 && iota != 0x7fffffff && better(v, iota, sm.rb_v[r], sm.rb_i[r])) {
-          sm.rb_v[r] = v;
-          sm.rb_i[r] = iota;
+        if (ln == 0 && bi != 0x7fffffff && better(bv, bi, sm.rb_v[r], sm.rb_i[r])) {
+          sm.rb_v[r] = bv;
+          sm.rb_i[r] = bi;
         }
       }
     }

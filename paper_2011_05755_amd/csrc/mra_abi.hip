@@ -37,6 +37,7 @@ struct Refset {
   int dmin = 0, dmax = 0;  // range of stencil floor offsets
   int variant = 0;         // correlation kernel tile configuration
   int chunk = 0;           // particles per chunk (0: from the workspace cap)
+  int prune = 1;           // exact pruning of the inverse FFT in the correlation kernel
 };
 
 struct Fail {
@@ -256,6 +257,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.row_cc = rcc;
   ca.row_idx = ridx;
   ca.table = table;
+  ca.prune = rs.prune;
   timed(c, "corr", [&] { hip_check(c, launch_corr(rs.g.precision, rs.variant, table != nullptr, ca, st), "corr"); });
   if (table) return;
 
@@ -409,7 +411,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     ca.B32 = rs.B32; ca.B16 = rs.B16;
     ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = pc.p.S; ca.M = pc.p.M;
     ca.maxabs = mx; ca.b_scale = rs.b_scale; ca.cs32 = c->cs32;
-    ca.row_cc = rcc + pc.row0; ca.row_idx = ridx + pc.row0; ca.table = nullptr;
+    ca.row_cc = rcc + pc.row0; ca.row_idx = ridx + pc.row0; ca.table = nullptr; ca.prune = rs.prune;
     cb.tile_start[i] = tile;
 
     MergeArgs& ma = mb.piece[i];
@@ -620,11 +622,12 @@ void iterate_impl(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts,
                   int32_t K, int32_t max_iter, double max_changed_frac, const mra_result* out, int32_t* counts,
                   int32_t* n_iter, int64_t* changed, bool by_flat) {
   // a tuning set on this refset id carries over when the geometry matches
-  int variant = -1, chunk = 0;
+  int variant = -1, chunk = 0, prune = 1;
   auto old = c->refs.find(id);
   if (old != c->refs.end() && old->second.K == K && std::memcmp(&old->second.g, g, sizeof(mra_geom)) == 0) {
     variant = old->second.variant;
     chunk = old->second.chunk;
+    prune = old->second.prune;
   }
   hipStream_t st = c->stream;
   mra_result o = *out;
@@ -639,6 +642,7 @@ void iterate_impl(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts,
       Refset& rs = c->refs[id];
       rs.variant = variant;
       rs.chunk = chunk;
+      rs.prune = prune;
     }
     align_impl(c, id, parts, N, -1, &o, nullptr);
     int64_t n_changed = N;
@@ -878,8 +882,10 @@ int mra_set_tuning(mra_ctx* c, int32_t id, const mra_tuning* t) {
     const int v = t->corr_variant < 0 ? corr_default_variant(rs.g.precision, rs.R4) : t->corr_variant;
     if (!corr_variant_ok(rs.g.precision, v, rs.R4)) throw Fail{MRA_E_INVAL, "variant cannot serve this geometry"};
     if (t->chunk_particles < 0) throw Fail{MRA_E_INVAL, "chunk_particles must be >= 0"};
+    if (t->prune < -1 || t->prune > 1) throw Fail{MRA_E_INVAL, "prune must be -1, 0 or 1"};
     rs.variant = v;
     rs.chunk = t->chunk_particles;
+    rs.prune = t->prune != 0;
   });
 }
 
@@ -889,6 +895,7 @@ int mra_get_tuning(mra_ctx* c, int32_t id, mra_tuning* t) {
     if (!t) throw Fail{MRA_E_INVAL, "tuning is NULL"};
     t->corr_variant = rs.variant;
     t->chunk_particles = rs.chunk;
+    t->prune = rs.prune;
   });
 }
 

@@ -58,6 +58,7 @@ struct CorrArgs {
   int* row_idx;          // [rows] flat index of the row's best
   float* table;          // debug: [n][K][M][S][256], else null
   const int* excl;       // per particle of the chunk: flat index left out of the arg-max, or null
+  int prune;             // 1: skip the inverse FFT of pairs whose CC bound is below the row's best
 };
 
 // Batched correlation: pieces of several stacks in one persistent launch.
