@@ -78,9 +78,17 @@ typedef struct mra_ctx mra_ctx;
  *             MRA_BF16 / MRA_FP16: contraction on 16-bit matrix cores with
  *             FP32 accumulation; polar sampling, FFTs, inverse FFTs and the
  *             arg-max stay FP32, and the winner's CC is re-scored in FP32.
- *  normalize  1: divide each reference by its weighted ring norm, 0: raw CC */
+ *  normalize  1: divide each reference by its weighted ring norm, 0: raw CC
+ *  rescore_rows  MRA_BF16 / MRA_FP16 only.  0 or 1: the FP32 re-score covers
+ *             the 16-bit winner alone.  k in 2..8: the winners of each
+ *             particle's k best rows (shifts) of the 16-bit pass, and their
+ *             neighbours one angle step either side (3k candidates), are
+ *             re-scored in FP32 and the best of them is the result, which
+ *             settles most near-ties that 16-bit rounding decides wrongly.
+ *             Ignored for MRA_FP32.  MRA_E_INVAL outside 0..8. */
 typedef struct mra_geom {
   int32_t L, r_min, r_max, n_phi, shift_max, mirror, precision, normalize;
+  int32_t rescore_rows;
 } mra_geom;
 
 /* Per-particle alignment parameters, structure of arrays of length N

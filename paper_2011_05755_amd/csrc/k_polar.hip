@@ -243,41 +243,138 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
 // FP32 re-score of each particle's winner: the direct double sum
 // sum_r w_r sum_j p_{s,m}[r][j] * qhat_k[r][(j + a) mod 256] with a = -psi.
 // The mirrored samples are the unmirrored stencil read at angle -j (the
-// stencil table is built symmetric in j <-> 256 - j).
-__device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, float* smem) {
-  float* img = smem;
-  double* red = reinterpret_cast<double*>(smem + ((a.Lp * a.Lp + 1) & ~1));
-  const int64_t gi = a.out_off + n;
-  stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
-  __syncthreads();
-  const int k = a.ref[gi], m = a.mirror[gi] ? 1 : 0;
-  const int sx = a.shift_x[gi], sy = a.shift_y[gi];
-  if (k < 0 || k >= a.K || sx < -a.T || sx > a.T || sy < -a.T || sy > a.T) {
-    if (threadIdx.x == 0) a.cc[gi] = NAN;
-    return;  // uniform over the block
-  }
-  const int lag = (kNphi - a.psi[gi]) & 255;
-  const int soff = sy * a.Lp + sx;
+// stencil table is built symmetric in j <-> 256 - j).  With a.rows >= 2 the
+// candidates are the winners of the particle's a.rows best rows of the 16-bit
+// pass and their neighbours one angle step either side; the best FP32 value
+// wins (ties: the smallest flat index) and replaces the parameters.
+constexpr int kMaxRescoreRows = 8;
+
+// FP32 CC of (ref k, shift soff, mirror m) at the lags lag0 + d, d < ND, for
+// the image staged in img; red holds ND x 256 doubles.  Reduction in a fixed
+// order (per-thread FP32 ring sum, then an FP64 tree), the same for every d.
+template <int ND>
+__device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* img, double* red, int k, int m,
+                                             int soff, int lag0, double (&out)[ND]) {
   const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
   const int j = threadIdx.x;
   const int jj = m ? ((kNphi - j) & 255) : j;
   const float* q = a.qhat + (size_t)k * a.R * kNphi;
-  float acc = 0.f;
+  float acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = 0.f;
   for (int r = 0; r < a.R; ++r) {
-    const Stencil s = a.stencil[r * kNphi + jj];
-    const float p = bilin(img, base + s.dy * a.Lp + s.dx + soff, a.Lp, s.fx, s.fy);
-    acc += (float)(a.r_min + r) * (p * q[r * kNphi + ((j + lag) & 255)]);
+    const Stencil st = a.stencil[r * kNphi + jj];
+    const float p = bilin(img, base + st.dy * a.Lp + st.dx + soff, a.Lp, st.fx, st.fy);
+    const float w = (float)(a.r_min + r);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] += w * (p * q[r * kNphi + ((j + lag0 + d) & 255)]);
   }
-  red[j] = (double)acc;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) red[d * 256 + j] = (double)acc[d];
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
-    if (j < h) red[j] += red[j + h];
+    if (j < h) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) red[d * 256 + j] += red[d * 256 + j + h];
+    }
     __syncthreads();
   }
-  if (j == 0) a.cc[gi] = (float)red[0];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) out[d] = red[d * 256];
+  __syncthreads();
 }
 
-static size_t rescore_lds_bytes(int Lp) { return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + 256 * sizeof(double); }
+__device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, float* smem) {
+  float* img = smem;
+  double* red = reinterpret_cast<double*>(smem + ((a.Lp * a.Lp + 1) & ~1));
+  int* cand = reinterpret_cast<int*>(red + 3 * 256);  // candidate rows' flat indices
+  const int64_t gi = a.out_off + n;
+  stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
+  if (a.rows <= 1) {
+    __syncthreads();
+    const int k = a.ref[gi], m = a.mirror[gi] ? 1 : 0;
+    const int sx = a.shift_x[gi], sy = a.shift_y[gi];
+    if (k < 0 || k >= a.K || sx < -a.T || sx > a.T || sy < -a.T || sy > a.T) {
+      if (threadIdx.x == 0) a.cc[gi] = NAN;
+      return;  // uniform over the block
+    }
+    double v[1];
+    rescore_lags<1>(a, img, red, k, m, sy * a.Lp + sx, (kNphi - a.psi[gi]) & 255, v);
+    if (threadIdx.x == 0) a.cc[gi] = (float)v[0];
+    return;
+  }
+  // the a.rows best rows of the 16-bit pass (thread 0; S is at most 289)
+  if (threadIdx.x == 0) {
+    float bv[kMaxRescoreRows];
+    int bi[kMaxRescoreRows];
+    const int nr = a.rows < kMaxRescoreRows ? a.rows : kMaxRescoreRows;
+    for (int i = 0; i < nr; ++i) {
+      bv[i] = -INFINITY;
+      bi[i] = 0x7fffffff;
+    }
+    for (int s = 0; s < a.S; ++s) {
+      float v = a.row_cc[(size_t)n * a.S + s];
+      int i = a.row_idx[(size_t)n * a.S + s];
+      if (i == 0x7fffffff) continue;
+      for (int t = 0; t < nr; ++t)  // insertion into the sorted list
+        if (v > bv[t] || (v == bv[t] && i < bi[t])) {
+          const float tv = bv[t];
+          const int ti = bi[t];
+          bv[t] = v;
+          bi[t] = i;
+          v = tv;
+          i = ti;
+        }
+    }
+    for (int t = 0; t < kMaxRescoreRows; ++t) cand[t] = t < nr ? bi[t] : 0x7fffffff;
+  }
+  __syncthreads();
+  float best = -INFINITY;
+  int best_i = 0x7fffffff;
+  for (int t = 0; t < kMaxRescoreRows; ++t) {
+    const int idx = cand[t];  // uniform
+    if (idx == 0x7fffffff) break;
+    const int ang = idx & 255;
+    int rest = idx >> 8;
+    const int s = rest % a.S;
+    rest /= a.S;
+    const int m = rest % a.M, k = rest / a.M;
+    const int sx = s % a.S1 - a.T, sy = s / a.S1 - a.T;
+    double v[3];
+    rescore_lags<3>(a, img, red, k, m, sy * a.Lp + sx, (ang + 255) & 255, v);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int i2 = (idx & ~255) | ((ang + 255 + d) & 255);
+      const float f = (float)v[d];
+      if (f > best || (f == best && i2 < best_i)) {
+        best = f;
+        best_i = i2;
+      }
+    }
+  }
+  if (threadIdx.x != 0) return;
+  if (best_i == 0x7fffffff) {  // the 16-bit pass found no candidate: keep its (invalid) result
+    a.cc[gi] = NAN;
+    return;
+  }
+  const int ang = best_i & 255;
+  int rest = best_i >> 8;
+  const int s = rest % a.S;
+  rest /= a.S;
+  const int m = rest % a.M, k = rest / a.M;
+  a.ref_w[gi] = k;
+  a.mirror_w[gi] = m;
+  a.shift_x_w[gi] = s % a.S1 - a.T;
+  a.shift_y_w[gi] = s / a.S1 - a.T;
+  a.psi_w[gi] = (kNphi - ang) & 255;
+  a.cc[gi] = best;
+  if (a.flat_w) a.flat_w[gi] = best_i;
+  if (a.win) a.win[n] = best_i;
+}
+
+static size_t rescore_lds_bytes(int Lp) {
+  return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + 3 * 256 * sizeof(double) + kMaxRescoreRows * sizeof(int);
+}
 
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
   extern __shared__ float smem[];

@@ -167,6 +167,7 @@ void check_geom(const mra_geom* g) {
   if (g->mirror != 0 && g->mirror != 1) bad("mirror must be 0 or 1");
   if (g->precision < 0 || g->precision > 2) bad("precision must be MRA_FP32, MRA_BF16 or MRA_FP16");
   if (g->normalize != 0 && g->normalize != 1) bad("normalize must be 0 or 1");
+  if (g->rescore_rows < 0 || g->rescore_rows > 8) bad("rescore_rows must be in [0, 8]");
 }
 
 Refset& get_refset(mra_ctx* c, int32_t id) {
@@ -284,6 +285,12 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
     ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
     ra.psi = out->psi; ra.mirror = out->mirror;
     ra.cc = out->cc;
+    ra.rows = rs.g.rescore_rows;
+    ra.S1 = p.S1; ra.S = p.S; ra.M = p.M;
+    ra.row_cc = rcc; ra.row_idx = ridx;
+    ra.ref_w = out->ref; ra.shift_x_w = out->shift_x; ra.shift_y_w = out->shift_y;
+    ra.psi_w = out->psi; ra.mirror_w = out->mirror; ra.flat_w = out->flat_index;
+    ra.win = win;
     timed(c, "rescore", [&] { hip_check(c, launch_rescore(ra, st), "rescore"); });
   }
 
@@ -427,6 +434,11 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     ra.K = rs.K; ra.T = pc.p.T; ra.stencil = rs.stencil; ra.qhat = rs.qhat;
     ra.ref = sk.out.ref; ra.shift_x = sk.out.shift_x; ra.shift_y = sk.out.shift_y; ra.psi = sk.out.psi;
     ra.mirror = sk.out.mirror; ra.cc = sk.out.cc;
+    ra.rows = rs.g.rescore_rows; ra.S1 = pc.p.S1; ra.S = pc.p.S; ra.M = pc.p.M;
+    ra.row_cc = rcc + pc.row0; ra.row_idx = ridx + pc.row0;
+    ra.ref_w = sk.out.ref; ra.shift_x_w = sk.out.shift_x; ra.shift_y_w = sk.out.shift_y;
+    ra.psi_w = sk.out.psi; ra.mirror_w = sk.out.mirror; ra.flat_w = sk.out.flat_index;
+    ra.win = nullptr;
     rb.start[i] = part;
 
     part += pc.nc;

@@ -90,6 +90,14 @@ struct RescoreArgs {
   const float* qhat;     // [K][R][256]
   const int32_t *ref, *shift_x, *shift_y, *psi, *mirror;
   float* cc;
+  // Re-ranking (rows >= 2): the winners of the particle's `rows` best rows of
+  // the 16-bit pass and their neighbours within +-1 angle are re-scored in
+  // FP32 and the best of them becomes the result.  rows <= 1: the winner only.
+  int rows, S1, S, M;
+  const float* row_cc;   // [n_part][S] of the 16-bit pass
+  const int* row_idx;
+  int32_t *ref_w, *shift_x_w, *shift_y_w, *psi_w, *mirror_w, *flat_w;  // re-ranked outputs
+  int32_t* win;          // chunk-local winner copy for the runner-up pass, or null
 };
 
 // Batched forms of the per-particle kernels: item i of the launch is
