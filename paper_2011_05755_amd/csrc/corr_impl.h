@@ -408,7 +408,12 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
   if constexpr (PREC == kFP32) con.load_a(a, tile, w, ln);
   else con.load_a(a, tile, w, ln, PREC == kFP16 ? fp16_scale(a, tile * kRowTile + (ln & 7)) : 1.f);
   int* list = sm.list + w * 64;
-  const bool prune = MODE != kTable && a.prune;
+  // Pruning (not in table mode, and not with 4 waves, whose registers are
+  // full with the resident operand) stops for the rest of the row tile when a
+  // reference tile after the second still leaves more than 56 of its 64 pairs
+  // live: the bound then costs more than it saves (references that are
+  // themselves noisy images).
+  bool prune = MODE != kTable && NW == 8 && a.prune;
 
   for (int kt = 0; kt < a.n_ref_tiles; ++kt) {
     // ---------------- contraction on the matrix cores ----------------
@@ -467,6 +472,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
       live = __ballot(keep);
     }
     const int n_live = __popcll(live);
+    if (prune && kt >= 2 && n_live > 56) prune = false;  // wave-uniform
     {
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
       if ((live >> ln) & 1) list[rank] = ln;
