@@ -29,6 +29,7 @@ from .mra_oracle import (  # noqa: F401
     polar_positions,
     polar_samples,
     reference_polar,
+    refine_psi,
     rfa,
     ring_radii,
     ring_weights,

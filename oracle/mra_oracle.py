@@ -19,7 +19,7 @@ float64 and evaluates the paper's definitions directly:
 
 Readings of points the paper leaves open (centre, axes, interpolation, edge,
 normalisation, lag direction, tie rule, mirror axis) are fixed in
-``Geometry`` and in the docstrings below; each is listed in the design doc.
+``Geometry`` and in the docstrings below.
 
 Nothing here uses an FFT: the CC is the direct sum over rings and angles.  The
 only library primitive is a float64 matrix product that evaluates many of
@@ -382,3 +382,29 @@ def rfa(parts: np.ndarray, g: Geometry, max_iter: int = 10, max_changed_frac: fl
                 break
         prev = params["flat_index"].copy()
     return params, Y[0], it, fracs
+
+
+def refine_psi(parts: np.ndarray, refs: np.ndarray, g: Geometry, params: dict) -> np.ndarray:
+    """Sub-step in-plane angle of each particle's winner (an optional
+    refinement; the paper searches integer angle steps only).
+
+    A parabola through the CC at the winning lag a and at a - 1, a + 1
+    (direct double sums) peaks at a + d with
+    d = (c(a-1) - c(a+1)) / (2 (c(a-1) - 2 c(a) + c(a+1))); d = 0 when the
+    three values do not curve downwards, and d is clamped to [-1/2, 1/2].
+    The refined angle, in steps of 2 pi / n_phi like psi, is (psi - d) mod
+    n_phi (psi = -a).
+    """
+    parts = np.asarray(parts)
+    qhat, _ = reference_polar(refs, g)
+    out = np.empty(parts.shape[0])
+    for n in range(parts.shape[0]):
+        k, m = int(params["ref"][n]), int(params["mirror"][n])
+        sx, sy, psi = int(params["shift_x"][n]), int(params["shift_y"][n]), int(params["psi"][n])
+        a = (g.n_phi - psi) % g.n_phi
+        cm, c0, cp = (candidate_cc(parts[n], qhat[k], g, sx, sy, m, (a + d) % g.n_phi) for d in (-1, 0, 1))
+        den = cm - 2.0 * c0 + cp
+        d = 0.5 * (cm - cp) / den if den < 0.0 else 0.0
+        d = min(0.5, max(-0.5, d))
+        out[n] = (psi - d) % g.n_phi
+    return out
