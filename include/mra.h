@@ -106,6 +106,12 @@ typedef struct mra_result {
                           contraction pass with the winner left out, in the
                           form's contraction precision.  NULL skips the pass. */
   int32_t* flat_index; /* optional: iota of the winner                      */
+  float* psi_frac;     /* optional: sub-step in-plane angle in psi's units
+                          (steps of 2 pi / n_phi, in [0, n_phi)): a parabola
+                          through the FP32 CC at the winning angle and its two
+                          neighbours peaks at a + d, |d| <= 1/2 (d = 0 if the
+                          three do not curve down); psi_frac = psi - d.  One
+                          more pass over the images; NULL skips it.          */
 } mra_result;
 
 /* One stack of an uneven batch (mra_align_batch). */
@@ -255,7 +261,8 @@ int mra_debug_refs(mra_ctx* ctx, int32_t refset_id, float* qhat, double* norm);
 /* Kernel timing for measurement.  mra_profile(ctx, 1) clears and starts
  * recording a HIP event pair around every launch of the named kernel groups
  * ("polar", "corr", "merge", "rescore", "maxabs", "averages", "corr2" for
- * the runner-up pass of cc2, and "rfa" for the fused K = 1 kernel) on the context's stream;
+ * the runner-up pass of cc2, "rfa" for the fused K = 1 kernel and "refine"
+ * for psi_frac) on the context's stream;
  * mra_profile(ctx, 0) stops.  mra_profile_read synchronises the stream and
  * returns the summed device time and the launch count of one group. */
 int mra_profile(mra_ctx* ctx, int enable);

@@ -403,6 +403,42 @@ hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Sub-step angle of each particle's final winner: the FP32 CC at lags
+// a - 1, a, a + 1 (a = -psi) and the vertex of the parabola through them.
+__global__ __launch_bounds__(256) void k_refine(RescoreArgs a) {
+  extern __shared__ float smem[];
+  float* img = smem;
+  double* red = reinterpret_cast<double*>(smem + ((a.Lp * a.Lp + 1) & ~1));
+  const int n = blockIdx.x;
+  const int64_t gi = a.out_off + n;
+  stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
+  __syncthreads();
+  const int k = a.ref[gi], m = a.mirror[gi] ? 1 : 0;
+  const int sx = a.shift_x[gi], sy = a.shift_y[gi], psi = a.psi[gi];
+  if (k < 0 || k >= a.K || sx < -a.T || sx > a.T || sy < -a.T || sy > a.T) {
+    if (threadIdx.x == 0) a.psi_frac[gi] = NAN;
+    return;  // uniform over the block
+  }
+  const int ang = (kNphi - psi) & 255;
+  double v[3];
+  rescore_lags<3>(a, img, red, k, m, sy * a.Lp + sx, (ang + 255) & 255, v);
+  if (threadIdx.x == 0) {
+    const double den = v[0] - 2.0 * v[1] + v[2];
+    double d = den < 0.0 ? 0.5 * (v[0] - v[2]) / den : 0.0;
+    d = d < -0.5 ? -0.5 : (d > 0.5 ? 0.5 : d);
+    double f = (double)psi - d;
+    if (f < 0.0) f += kNphi;
+    if (f >= kNphi) f -= kNphi;
+    a.psi_frac[gi] = (float)f;
+  }
+}
+
+hipError_t launch_refine(const RescoreArgs& a, hipStream_t st) {
+  if (a.n_part <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine, dim3(a.n_part), dim3(256), rescore_lds_bytes(a.Lp), st, a);
+  return hipGetLastError();
+}
+
 // max |pixel| of each particle image (the FP16 operand scale): one
 // workgroup per particle, out[n] for n < n_part.
 __global__ __launch_bounds__(256) void k_part_maxabs(const float* x, int LL, float* out) {

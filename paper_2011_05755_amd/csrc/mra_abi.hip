@@ -213,6 +213,27 @@ int64_t chunk_particles(mra_ctx* c, const Refset& rs, const Plan& p) {
   return std::max<int64_t>(n, 1);
 }
 
+// Sub-step angles of particles n0 .. n0 + nc - 1 from their final parameters.
+void refine_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, int64_t n0, int64_t nc,
+                  const mra_result* out) {
+  const int L = rs.g.L;
+  const int64_t step = INT32_MAX / 2;
+  for (int64_t o = 0; o < nc; o += step) {
+    RescoreArgs ra{};
+    ra.parts = parts + (size_t)(n0 + o) * L * L;
+    ra.n_part = (int)std::min<int64_t>(step, nc - o);
+    ra.out_off = n0 + o;
+    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx;
+    ra.K = rs.K; ra.T = p.T;
+    ra.stencil = rs.stencil;
+    ra.qhat = rs.qhat;
+    ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
+    ra.psi = out->psi; ra.mirror = out->mirror;
+    ra.psi_frac = out->psi_frac;
+    timed(c, "refine", [&] { hip_check(c, launch_refine(ra, c->stream), "refine"); });
+  }
+}
+
 // One chunk of the alignment pass: resample + FFT -> correlation -> merge
 // (-> FP32 re-score for 16-bit contractions).  mode 0 = production,
 // mode 3 = debug CC table into `table`.
@@ -304,6 +325,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
     m2.runner_up = 1;
     timed(c, "merge", [&] { hip_check(c, launch_merge(m2, st), "merge"); });
   }
+  if (out->psi_frac) refine_chunk(c, rs, p, parts, n0, nc, out);
 }
 
 // One reference (K = 1): the fused single-reference kernel over the whole
@@ -326,6 +348,7 @@ void run_single(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts,
     ra.cc = out->cc; ra.cc2 = out->cc2;
     timed(c, "rfa", [&] { hip_check(c, launch_rfa(ra, c->stream), "rfa"); });
   }
+  if (out->psi_frac) refine_chunk(c, rs, p, parts, 0, N, out);
 }
 
 void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, const mra_result* out,
@@ -477,7 +500,7 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
       run_single(c, rs, p, s.parts, s.N, &s.out);
       continue;
     }
-    if (s.out.cc2) {  // runner-up requested: the per-chunk path, which runs the second pass
+    if (s.out.cc2 || s.out.psi_frac) {  // runner-up or refinement: the per-chunk path
       const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
       for (int64_t n0 = 0; n0 < s.N; n0 += step)
         run_chunk(c, rs, p, s.parts, n0, (int)std::min<int64_t>(step, s.N - n0), &s.out, nullptr);

@@ -98,6 +98,7 @@ struct RescoreArgs {
   const int* row_idx;
   int32_t *ref_w, *shift_x_w, *shift_y_w, *psi_w, *mirror_w, *flat_w;  // re-ranked outputs
   int32_t* win;          // chunk-local winner copy for the runner-up pass, or null
+  float* psi_frac;       // refinement launch: sub-step angle of the final winner
 };
 
 // Batched forms of the per-particle kernels: item i of the launch is
@@ -145,6 +146,7 @@ hipError_t launch_rescore(const RescoreArgs& a, hipStream_t st);
 hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st);
 hipError_t launch_merge_batch(const MergeBatch& b, hipStream_t st);
 hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st);
+hipError_t launch_refine(const RescoreArgs& a, hipStream_t st);  // psi_frac from the final parameters
 hipError_t launch_part_maxabs(const float* x, int n_part, int L, float* out, hipStream_t st);
 hipError_t launch_rfa(const RfaArgs& a, hipStream_t st);
 // count[0] += #{i : cls[i] != prev[i]}; then prev = cls

@@ -40,7 +40,7 @@ class Geom(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("ref", ctypes.c_void_p), ("shift_x", ctypes.c_void_p), ("shift_y", ctypes.c_void_p),
                 ("psi", ctypes.c_void_p), ("mirror", ctypes.c_void_p), ("cc", ctypes.c_void_p),
-                ("cc2", ctypes.c_void_p), ("flat_index", ctypes.c_void_p)]
+                ("cc2", ctypes.c_void_p), ("flat_index", ctypes.c_void_p), ("psi_frac", ctypes.c_void_p)]
 
 
 class Stack(ctypes.Structure):
@@ -120,19 +120,22 @@ class AlignResult:
     cc: torch.Tensor
     cc2: torch.Tensor | None = None
     flat_index: torch.Tensor | None = None
+    psi_frac: torch.Tensor | None = None
 
     @classmethod
-    def empty(cls, N: int, device, with_cc2=False, with_flat=True):
+    def empty(cls, N: int, device, with_cc2=False, with_flat=True, with_psi_frac=False):
         i = dict(dtype=torch.int32, device=device)
+        f = dict(dtype=torch.float32, device=device)
         return cls(ref=torch.empty(N, **i), shift_x=torch.empty(N, **i), shift_y=torch.empty(N, **i),
                    psi=torch.empty(N, **i), mirror=torch.empty(N, **i),
-                   cc=torch.empty(N, dtype=torch.float32, device=device),
-                   cc2=torch.empty(N, dtype=torch.float32, device=device) if with_cc2 else None,
-                   flat_index=torch.empty(N, **i) if with_flat else None)
+                   cc=torch.empty(N, **f),
+                   cc2=torch.empty(N, **f) if with_cc2 else None,
+                   flat_index=torch.empty(N, **i) if with_flat else None,
+                   psi_frac=torch.empty(N, **f) if with_psi_frac else None)
 
     def c_struct(self) -> Result:
         return Result(*(_ptr(getattr(self, f)) for f in
-                        ("ref", "shift_x", "shift_y", "psi", "mirror", "cc", "cc2", "flat_index")))
+                        ("ref", "shift_x", "shift_y", "psi", "mirror", "cc", "cc2", "flat_index", "psi_frac")))
 
     def narrow(self, lo: int, n: int) -> "AlignResult":
         return AlignResult(**{f.name: (None if getattr(self, f.name) is None else getattr(self, f.name)[lo:lo + n])
@@ -229,12 +232,12 @@ class Context:
 
     # ---- alignment ----
     def align(self, refset_id: int, parts: torch.Tensor, out: AlignResult | None = None,
-              with_cc2: bool = False) -> AlignResult:
+              with_cc2: bool = False, with_psi_frac: bool = False) -> AlignResult:
         rs = self.refsets[refset_id]
         _check_images(parts, rs.L, "parts")
         N = parts.shape[0]
         if out is None:
-            out = AlignResult.empty(N, parts.device, with_cc2=with_cc2)
+            out = AlignResult.empty(N, parts.device, with_cc2=with_cc2, with_psi_frac=with_psi_frac)
         res = out.c_struct()
         self._check(self.lib.mra_align(self._h, refset_id, _ptr(parts), N, ctypes.byref(res)))
         return out

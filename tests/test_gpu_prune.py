@@ -59,6 +59,19 @@ def test_pruning_changes_no_result(ctx, form, variants, snr):
         same(off, on, f"{form} v{v}")
 
 
+@pytest.mark.parametrize("mirror,normalize,r_min", [(False, True, 1), (True, False, 3)])
+def test_pruning_without_mirror_or_normalisation(ctx, mirror, normalize, r_min):
+    L, K, T, N = 48, 13, 1, 19
+    blobs = synth.make_blobs(K, L, seed=(93, 0), rho_max=20)
+    refs = synth.render_refs(blobs).to(DEV)
+    parts = synth.make_particles(blobs, N, T, 0.2, seed=(93, 1), device=DEV, mirror=mirror)[0]
+    for form in ("fp32", "bf16"):
+        ctx.load_refs(86, refs, r_min=r_min, r_max=20, shift_max=T, precision=form, mirror=mirror,
+                      normalize=normalize)
+        off, on = run_both(ctx, 86, parts, with_cc2=True)
+        same(off, on, f"{form} mirror={mirror} normalize={normalize}")
+
+
 def test_pruning_in_the_batched_launch(ctx):
     from paper_2011_05755_amd import mra
     stacks, want = [], []
