@@ -76,13 +76,16 @@ struct Op16<kFP16> {
 };
 
 // Particle operand of lane ln for slot `slot`: ring g*R4 + t of lane group
-// g = ln/16 at element t*16 (A layout [tile][slot][ring][16]).  Rings >= R
+// g = ln/16 at element t * kRingStride (A layout [tile][ring][slot][16],
+// the slot at slot_pos(slot) for the FP32 contraction, PERM).  Rings >= R
 // are padding that the polar kernel never writes: callers mask them.
 // RX > 0: R4 == RX is known at compile time.
-template <int RX = 0>
+constexpr int kRingStride = kSlots * 16;
+template <int RX = 0, bool PERM = false>
 __device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int slot, int ln) {
   const int R4 = RX > 0 ? RX : a.R4;
-  return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
+  const int pos = PERM ? slot_pos(slot) : slot;
+  return a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + pos) * 16 + (ln & 15);
 }
 // Element t of the lane's operand: ring (ln/16)*R4 + t.  The load is never
 // conditional (a conditional load waits for its data before the next one is
@@ -94,7 +97,7 @@ template <int RX = 0>
 __device__ __forceinline__ float a_elem(const CorrArgs& a, const float* ap, int ln, int t, bool nt) {
   const int R4 = RX > 0 ? RX : a.R4;
   const int tt = t < R4 ? t : R4 - 1;
-  const float x = nt ? __builtin_nontemporal_load(ap + tt * 16) : ap[tt * 16];
+  const float x = nt ? __builtin_nontemporal_load(ap + tt * kRingStride) : ap[tt * kRingStride];
   uint32_t keep = (t < R4 && (ln >> 4) * R4 + t < a.R) ? 0xffffffffu : 0u;
   asm("" : "+v"(keep));
   return __uint_as_float(__float_as_uint(x) & keep);
@@ -139,7 +142,7 @@ struct Fp32Contract {
     if constexpr (RES) {
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
-        const float* ap = a_lane<RX>(a, tile, w + NW * i, ln);
+        const float* ap = a_lane<RX, true>(a, tile, w + NW * i, ln);
 #pragma unroll
         for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<RX>(a, ap, ln, t, true);
       }
@@ -184,7 +187,7 @@ struct Fp32Contract {
       // that the slot loop need not be unrolled)
       float b0[MAXR], a0[MAXR], b1[MAXR], a1[MAXR];
       auto loada = [&](int i, float (&dst)[MAXR]) {
-        const float* ap = a_lane<RX>(a, tile, w + NW * i, ln);
+        const float* ap = a_lane<RX, true>(a, tile, w + NW * i, ln);
 #pragma unroll
         for (int t = 0; t < MAXR; ++t) dst[t] = a_elem<RX>(a, ap, ln, t, false);
       };

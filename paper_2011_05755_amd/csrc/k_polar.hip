@@ -4,14 +4,17 @@
 //
 // One 4-wave workgroup per particle (about 50 KB of LDS at L = 76, so three
 // workgroups share a CU).  The image is staged once in LDS with a zero
-// border (coalesced HBM read); the (ring, 8-row group) items of the
-// particle are split between the waves.  In an item, lane (l, row) takes the
-// 32 samples p[16 n1 + 2l + e] of shift `row` (integer shifts move the
-// bilinear stencil by whole pixels, so all shifts share one stencil table,
-// read from the cache).  The 256-point real FFT runs as a 16 x 8 complex FFT
-// across the eight lanes l of a shift, with a transpose through a per-wave
-// LDS scratch, and the spectra are staged there again so that the operand is
-// written in whole 64-byte segments.
+// border (coalesced HBM read), beside a float-float cos/sin table; the
+// (ring, 8-row group) items of the particle are split between the waves.
+// In an item, lane (l, row) takes the 32 samples p[16 n1 + 2l + e] of shift
+// `row`, positions computed from the table (integer shifts move the
+// bilinear taps by whole pixels), so the item loop issues no memory loads.
+// The 256-point real FFT runs as a 16 x 8 complex FFT across the eight
+// lanes l of a shift, with a transpose through a per-wave LDS scratch, and
+// the spectra are staged there again so that an item's 128 slots of one
+// ring are written as one contiguous 8 KB run of the operand (the kernel is
+// bound by its HBM writes, and runs of 64-byte pieces scattered over the
+// tile write far slower).
 #include "mra_common.h"
 #include "mra_fft.h"
 #include "polar_impl.h"
@@ -30,16 +33,17 @@ template <int MODE>
 __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float* smem) {
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
-  float2* tw = scr + kPolarWaves * 64 * 9;  // exp(-2 pi i e / 256), e = 0..255
+  CosSin* cs = reinterpret_cast<CosSin*>(scr + kPolarWaves * 64 * 9);
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
-  if (threadIdx.x < kNphi) tw[threadIdx.x] = w256f(a.cs32, threadIdx.x);
+  stage_cs(cs, a.cs64);
   __syncthreads();
 
-  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
   const int l = ln >> 3, rl = ln & 7;
   float2* my = scr + w * 64 * 9;                // per-wave scratch: 64 lanes x 9 float2
   float* stage = reinterpret_cast<float*>(my);  // [64 slots][16] in each staging round
   const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
+  const int Lp4 = 4 * a.Lp, s1m = (65536 + a.S1 - 1) / a.S1;
   // lane rl handles row (q0 + grp) * 8 + rl: groups are aligned to the
   // correlation kernel's 8-row tiles
   const int row0 = n * a.S;
@@ -63,26 +67,15 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
     const int s = row - row0;
     const bool valid = s >= 0 && s < a.S;
     const int sc = s < 0 ? 0 : (s < a.S ? s : a.S - 1);
-    const int soff = (sc / a.S1 - a.T) * a.Lp + (sc % a.S1 - a.T);
+    const int o4 = 4 * (base + shift_offset(sc, a.S1, s1m, a.T, a.Lp));
 
-    // 32 bilinear samples p[16 n1 + 2 l + e] of this lane's shift; the
-    // stencils (shared by all shifts) are read from the cache in two
-    // batches of 16 rather than pinned in registers
-    const Stencil* sp = a.stencil + ring * kNphi + 2 * lx;
+    // 32 bilinear samples p[16 n1 + 2 l + e] of this lane's shift, the
+    // positions taken from the staged cos/sin (no memory loads in the loop)
+    const float rr = (float)(a.r_min + ring);
+    const CosSin* cp = cs + 2 * lx;
     float v[32];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      Stencil st[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int i = 16 * h + j;
-        st[j] = sp[16 * (i >> 1) + (i & 1)];
-      }
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        v[16 * h + j] = bilin(img, base + __mul24(st[j].dy, a.Lp) + st[j].dx + soff, a.Lp, st[j].fx, st[j].fy);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int i = 0; i < 32; ++i) v[i] = polar_tap(img, o4, Lp4, rr, cp[16 * (i >> 1) + (i & 1)]);
 
     if (MODE == 1) {
       if (valid) {
@@ -98,7 +91,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
     for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
     dft16<-1>(z);
 #pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((lx * k1) & 127)]);
+    for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], twid(cs, 2 * ((lx * k1) & 127)));
     // transpose through the scratch in two halves: lane l's first column
     // k1a lies in 0..7, its second k1b in 8..15.  Entries are ordered
     // (l, shift) with the shift fastest, which spreads a wave's accesses
@@ -122,15 +115,16 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
     if (MODE == 0) {
       // Every real split yields one slot below 64 and one above (128 - f, or
       // lane 0's 0 and 64): keep both, then stage [slot][p*8 + row] for the
-      // 64 low slots and then the 64 high ones, and write whole 64-byte
-      // (slot, ring) segments of the tile with 16-byte stores.  The four
+      // 64 low slots and then the 64 high ones, and write the 64-byte
+      // (ring, slot) segments of the tile with 16-byte stores, each store
+      // instruction covering whole 128-byte lines.  The four
       // 16-byte chunks of a slot are XOR-swizzled by slot & 3, so the eight
       // lanes l that write at once hit distinct banks.
       int lo_s[8], hi_s[8];
       float lo_a[8], lo_b[8], hi_a[8], hi_b[8];
       int e = 0, s0 = 0;
       float a0 = 0.f, b0 = 0.f;
-      fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
+      fwd_emit(lx, Za, Zb, [&](int f) { return twid(cs, f & 255); },
                [&](int slot, float re, float im) {
                  const int k = e >> 1;
                  if ((e++ & 1) == 0) {
@@ -148,14 +142,16 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       const int tile = q0 + grp;
       const int first = row0 - tile * 8;            // rows of this tile before the particle
       const int last = row0 + a.S - tile * 8;       // first row after the particle
-      float* dst = a.out + (size_t)tile * kSlots * a.R4 * 64 + ring * 16;
-      const size_t slot_stride = (size_t)a.R4 * 64;
+      float* dst = a.out + ((size_t)tile * 4 * a.R4 + ring) * kSlots * 16;
       const int part = lnx & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
       const int r0 = (part & 1) * 4;
       const bool full = r0 >= first && r0 + 4 <= last;
-      // the lane's segment of slot 16 * it + (lane / 4) + 64 * h: one vector
-      // multiply per item, the rest is a uniform offset
-      float* const lane_dst = dst + (size_t)__mul24(lnx >> 2, (int)slot_stride) + part * 4;
+      // the lane's segment of slot s = 64 h + 16 it + j (j = lane / 4) sits at
+      // s, or at slot_pos(s) = (j & 7) * 16 + (j >> 3) + 8 h + 2 it: a
+      // per-lane part computed once per item and a uniform offset
+      const int j = lnx >> 2;
+      const bool perm = a.slot_perm != 0;
+      float* const lane_dst = dst + (perm ? (j & 7) * 16 + (j >> 3) : j) * 16 + part * 4;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -170,7 +166,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         for (int it = 0; it < 4; ++it) {
           const int sl = it * 16 + (lnx >> 2);
           const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
-          float* o = lane_dst + (size_t)(64 * h + 16 * it) * slot_stride;
+          float* o = lane_dst + (perm ? 8 * h + 2 * it : 64 * h + 16 * it) * 16;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;
           } else {
@@ -184,7 +180,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       }
     } else {  // MODE 2: plain spectra
       float* o = a.out + (((size_t)n * a.S + (valid ? s : 0)) * a.R + ring) * 129 * 2;
-      fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; },
+      fwd_emit(lx, Za, Zb, [&](int f) { return twid(cs, f & 255); },
                [&](int slot, float re, float im) {
                  if (!valid) return;
                  if (slot == 0) {
@@ -217,7 +213,8 @@ __global__ __launch_bounds__(kPolarThreads) void k_polar_batch(PolarBatch b) {
 }
 
 size_t polar_lds_bytes(int Lp) {
-  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)(kPolarWaves * 64 * 9 + kNphi) * sizeof(float2);
+  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)kPolarWaves * 64 * 9 * sizeof(float2) +
+         (size_t)kNphi * sizeof(CosSin);
 }
 
 hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st) {
@@ -264,7 +261,7 @@ __device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* 
   for (int d = 0; d < ND; ++d) acc[d] = 0.f;
   for (int r = 0; r < a.R; ++r) {
     const Stencil st = a.stencil[r * kNphi + jj];
-    const float p = bilin(img, base + st.dy * a.Lp + st.dx + soff, a.Lp, st.fx, st.fy);
+    const float p = bilin(img, base + st.dy * a.Lp + (st.bx >> 2) + soff, a.Lp, st.fx, st.fy);
     const float w = (float)(a.r_min + r);
 #pragma unroll
     for (int d = 0; d < ND; ++d) acc[d] += w * (p * q[r * kNphi + ((j + lag0 + d) & 255)]);

@@ -51,17 +51,18 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
   extern __shared__ float smem[];
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
-  float2* tw = scr + kPolarWaves * 64 * 9;        // exp(-2 pi i e / 256)
+  CosSin* cs = reinterpret_cast<CosSin*>(scr + kPolarWaves * 64 * 9);
   float4* V = reinterpret_cast<float4*>(scr);     // summed spectra; aliases the scratch between groups
   const int n = blockIdx.x;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
-  if (threadIdx.x < kNphi) tw[threadIdx.x] = w256f(a.cs32, threadIdx.x);
+  stage_cs(cs, a.cs64);
   __syncthreads();
 
-  const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
   const int l = ln >> 3, rl = ln & 7;
   float2* my = scr + w * 64 * 9;                  // per-wave transposition scratch
   const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
+  const int Lp4 = 4 * a.Lp, s1m = (65536 + a.S1 - 1) / a.S1;
   Best best{-INFINITY, INT_MAX, -INFINITY};
   const int ngrp = (a.S + 7) >> 3;
 
@@ -79,30 +80,20 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
       fwd_cols(lx, k1a, k1b);
       const int s = grp * 8 + rx;
       const int sc = s < a.S ? s : a.S - 1;       // rows past the last shift repeat it (never chosen)
-      const int soff = (sc / a.S1 - a.T) * a.Lp + (sc % a.S1 - a.T);
+      const int o4 = 4 * (base + shift_offset(sc, a.S1, s1m, a.T, a.Lp));
 
-      const Stencil* sp = a.stencil + ring * kNphi + 2 * lx;
+      const float rr = (float)(a.r_min + ring);
+      const CosSin* cp = cs + 2 * lx;
       float v[32];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        Stencil st[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int i = 16 * h + j;
-          st[j] = sp[16 * (i >> 1) + (i & 1)];
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          v[16 * h + j] = bilin(img, base + __mul24(st[j].dy, a.Lp) + st[j].dx + soff, a.Lp, st[j].fx, st[j].fy);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      for (int i = 0; i < 32; ++i) v[i] = polar_tap(img, o4, Lp4, rr, cp[16 * (i >> 1) + (i & 1)]);
 
       float2 z[16];
 #pragma unroll
       for (int n1 = 0; n1 < 16; ++n1) z[n1] = make_float2(v[2 * n1], v[2 * n1 + 1]);
       dft16<-1>(z);
 #pragma unroll
-      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], tw[2 * ((lx * k1) & 127)]);
+      for (int k1 = 1; k1 < 16; ++k1) z[k1] = cmul(z[k1], twid(cs, 2 * ((lx * k1) & 127)));
       float2 Za[8], Zb[8];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -121,7 +112,7 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
 
       const float2* G = a.G + ring * kSlots;
       int e = 0;
-      fwd_emit(lx, Za, Zb, [&](int f) { return tw[f & 255]; }, [&](int slot, float re, float im) {
+      fwd_emit(lx, Za, Zb, [&](int f) { return twid(cs, f & 255); }, [&](int slot, float re, float im) {
         const float al = re - im, be = re + im;
         const float2 g = G[slot];                 // (c - d, c + d)
         acc[e][0] += al * g.x;
@@ -167,7 +158,7 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
         const float4 u = V[row * kRowStride + (up ? ((256 - e) & 127) : e)];
         x[k1] = up ? make_float2(u.z, u.w) : make_float2(u.x, u.y);
       }
-      inv_pass1(q, x, [&](int e) { return tw[e & 255]; });
+      inv_pass1(q, x, [&](int e) { return twid(cs, e & 255); });
     }
     wave_sync();  // the wave's two rows are read before they are overwritten
     if (ln < 32) {

@@ -178,6 +178,7 @@ Refset& get_refset(mra_ctx* c, int32_t id) {
 
 struct Plan {
   int T, S1, S, M, pad, Lp, cx;
+  int pad_r, Lp_r;  // border and side for the kernels that sample with the FP64 stencil table
 };
 
 Plan plan_for(const Refset& rs, int T) {
@@ -188,9 +189,13 @@ Plan plan_for(const Refset& rs, int T) {
   p.S = p.S1 * p.S1;
   p.M = rs.g.mirror ? 2 : 1;
   p.cx = rs.g.L / 2;
-  const int lo = p.cx - T + rs.dmin;          // lowest pixel index touched
-  const int hi = p.cx + T + rs.dmax + 1;      // highest
-  p.pad = std::max(0, std::max(-lo, hi - (rs.g.L - 1)));
+  // lowest and highest pixel index touched; the resamplers that take the
+  // floor of single-precision positions reach one pixel further either side
+  const int lo = p.cx - T + rs.dmin;
+  const int hi = p.cx + T + rs.dmax + 1;
+  p.pad_r = std::max(0, std::max(-lo, hi - (rs.g.L - 1)));
+  p.Lp_r = rs.g.L + 2 * p.pad_r;
+  p.pad = std::max(0, std::max(-(lo - 1), hi + 1 - (rs.g.L - 1)));
   p.Lp = rs.g.L + 2 * p.pad;
   if (polar_lds_bytes(p.Lp) > kLdsMax)
     throw Fail{MRA_E_INVAL, "box plus search range too large for the LDS-staged resampler"};
@@ -223,7 +228,7 @@ void refine_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* part
     ra.parts = parts + (size_t)(n0 + o) * L * L;
     ra.n_part = (int)std::min<int64_t>(step, nc - o);
     ra.out_off = n0 + o;
-    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx;
+    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = p.Lp_r; ra.pad = p.pad_r; ra.cx = p.cx;
     ra.K = rs.K; ra.T = p.T;
     ra.stencil = rs.stencil;
     ra.qhat = rs.qhat;
@@ -261,8 +266,9 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   pa.n_part = nc;
   pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
   pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx;
-  pa.stencil = rs.stencil;
-  pa.cs32 = c->cs32;
+  pa.r_min = rs.g.r_min;
+  pa.slot_perm = rs.g.precision == kFP32;
+  pa.cs64 = c->cs64;
   pa.out = A;
   timed(c, "polar", [&] { hip_check(c, launch_polar(0, pa, st), "polar"); });
 
@@ -299,7 +305,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
     ra.parts = src;
     ra.n_part = nc;
     ra.out_off = n0;
-    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx;
+    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = p.Lp_r; ra.pad = p.pad_r; ra.cx = p.cx;
     ra.K = rs.K; ra.T = p.T;
     ra.stencil = rs.stencil;
     ra.qhat = rs.qhat;
@@ -339,9 +345,8 @@ void run_single(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts,
     ra.n_part = (int)std::min<int64_t>(step, N - n0);
     ra.out_off = n0;
     ra.L = L; ra.R = rs.R; ra.T = p.T; ra.S1 = p.S1; ra.S = p.S; ra.M = p.M;
-    ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx;
-    ra.stencil = rs.stencil;
-    ra.cs32 = c->cs32;
+    ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx; ra.r_min = rs.g.r_min;
+    ra.cs64 = c->cs64;
     ra.G = rs.G1;
     ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
     ra.psi = out->psi; ra.mirror = out->mirror; ra.flat = out->flat_index;
@@ -433,7 +438,8 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     PolarArgs& pa = pb.piece[i];
     pa.parts = src; pa.n_part = pc.nc;
     pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = pc.p.T; pa.S1 = pc.p.S1; pa.S = pc.p.S;
-    pa.Lp = pc.p.Lp; pa.pad = pc.p.pad; pa.cx = pc.p.cx; pa.stencil = rs.stencil; pa.cs32 = c->cs32; pa.out = Ap;
+    pa.Lp = pc.p.Lp; pa.pad = pc.p.pad; pa.cx = pc.p.cx; pa.r_min = rs.g.r_min; pa.cs64 = c->cs64; pa.out = Ap;
+    pa.slot_perm = rs.g.precision == kFP32;
     pb.start[i] = part;
 
     CorrArgs& ca = cb.piece[i];
@@ -453,7 +459,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
 
     RescoreArgs& ra = rb.piece[i];
     ra.parts = src; ra.n_part = pc.nc; ra.out_off = pc.n0;
-    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = pc.p.Lp; ra.pad = pc.p.pad; ra.cx = pc.p.cx;
+    ra.L = L; ra.R = rs.R; ra.r_min = rs.g.r_min; ra.Lp = pc.p.Lp_r; ra.pad = pc.p.pad_r; ra.cx = pc.p.cx;
     ra.K = rs.K; ra.T = pc.p.T; ra.stencil = rs.stencil; ra.qhat = rs.qhat;
     ra.ref = sk.out.ref; ra.shift_x = sk.out.shift_x; ra.shift_y = sk.out.shift_y; ra.psi = sk.out.psi;
     ra.mirror = sk.out.mirror; ra.cc = sk.out.cc;
@@ -552,13 +558,13 @@ void load_refs_impl(mra_ctx* c, int32_t id, const float* refs, int32_t K, const 
         const double x = rr * cs[j], y = rr * sn[j];
         const double fx = std::floor(x), fy = std::floor(y);
         Stencil s;
-        s.dx = (int)fx;
+        s.bx = 4 * (int)fx;
         s.dy = (int)fy;
         s.fx = (float)(x - fx);
         s.fy = (float)(y - fy);
         sten[(size_t)r * kNphi + j] = s;
-        rs.dmin = std::min({rs.dmin, s.dx, s.dy});
-        rs.dmax = std::max({rs.dmax, s.dx, s.dy});
+        rs.dmin = std::min({rs.dmin, (int)fx, (int)fy});
+        rs.dmax = std::max({rs.dmax, (int)fx, (int)fy});
       }
     rs.stencil = (Stencil*)alloc(c, sten.size() * sizeof(Stencil), "stencil");
     hip_check(c, hipMemcpyAsync(rs.stencil, sten.data(), sten.size() * sizeof(Stencil), hipMemcpyHostToDevice, st), "memcpy");
@@ -875,7 +881,7 @@ int mra_debug_polar(mra_ctx* c, int32_t id, const float* parts, int64_t N, float
     PolarArgs pa{};
     pa.parts = parts; pa.n_part = (int)N;
     pa.L = rs.g.L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
-    pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx; pa.stencil = rs.stencil; pa.cs32 = c->cs32; pa.out = out;
+    pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx; pa.r_min = rs.g.r_min; pa.cs64 = c->cs64; pa.out = out;
     hip_check(c, launch_polar(1, pa, c->stream), "polar");
   });
 }
@@ -888,7 +894,7 @@ int mra_debug_spectra(mra_ctx* c, int32_t id, const float* parts, int64_t N, flo
     PolarArgs pa{};
     pa.parts = parts; pa.n_part = (int)N;
     pa.L = rs.g.L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
-    pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx; pa.stencil = rs.stencil; pa.cs32 = c->cs32; pa.out = out;
+    pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx; pa.r_min = rs.g.r_min; pa.cs64 = c->cs64; pa.out = out;
     hip_check(c, launch_polar(2, pa, c->stream), "polar");
   });
 }

@@ -10,6 +10,11 @@ namespace mra {
 
 constexpr int kNphi = 256;          // angles per ring (the paper's workloads)
 constexpr int kSlots = 128;         // frequency slots: f = 1..127, slot 0 = (f 0, f 128)
+
+// Position of slot s within a ring of the particle operand of the FP32
+// contraction: the slots s = w + 8 i that wave w of the correlation kernel
+// contracts are contiguous.  (The 16-bit contractions read slot s at s.)
+__host__ __device__ constexpr int slot_pos(int s) { return (s & 7) * 16 + (s >> 3); }
 constexpr int kRowTile = 8;         // particle rows (shift, particle) per correlation tile
 constexpr int kRefTile = 8;         // references per correlation tile
 constexpr int kPolarWaves = 4;      // resampling workgroup: 4 waves, 8 shifts x 8 FFT lanes each
@@ -20,15 +25,18 @@ constexpr int kAvgThreads = 256;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
-// Entry of the particle sampling stencil for ring r and angle j:
-// floor offsets (dx, dy) of r*(cos, sin)(theta_j) and the bilinear fractions.
+// Entry of the particle sampling stencil for ring r and angle j (FP64
+// positions, used by the FP32 re-score): the floor (dx, dy) of
+// r*(cos, sin)(theta_j), stored as bx = 4 dx (the byte offset of the column
+// in a float row) and dy, and the bilinear fractions.
 struct __attribute__((aligned(16))) Stencil {
-  int dx, dy;
+  int bx, dy;
   float fx, fy;
 };
 
 // Resample + ring-FFT kernel.  out layout depends on the mode:
-//  mode 0: correlation operand A, [row tile][slot][ring < 4*R4][16] float,
+//  mode 0: correlation operand A, [row tile][ring < 4*R4][slot][16] float
+//          (slot at slot_pos(slot) when slot_perm is set),
 //          inner index p*8 + row%8 (p = 0: a-b, p = 1: a+b); rings >= R are
 //          never written (the correlation kernel masks them)
 //  mode 1: polar samples [n][S][R][256]
@@ -38,14 +46,15 @@ struct PolarArgs {
   int n_part;
   int L, R, R4, T, S1, S;
   int Lp, pad, cx;     // LDS image side (with zero border), border width, centre
-  const Stencil* stencil;  // [R][256]
-  const float2* cs32;      // (cos, sin)(2 pi j / 256)
+  int r_min;           // radius of ring 0
+  int slot_perm;       // mode 0: slots at slot_pos (FP32 contraction) rather than in order
+  const double2* cs64; // (cos, sin)(2 pi j / 256)
   float* out;
 };
 
 // Fused contraction + inverse FFT over angle + arg-max.
 struct CorrArgs {
-  const float* A;        // [row tiles][128][4*R4][16]
+  const float* A;        // [row tiles][4*R4][128][16]
   int n_row_tiles;
   int rows;              // valid rows in the chunk (n * S)
   const float* B32;      // [ref tiles][128][R4][64]
@@ -125,9 +134,8 @@ struct RfaArgs {
   const float* parts;    // first particle of the call, [n][L][L]
   int n_part;
   int64_t out_off;
-  int L, R, T, S1, S, M, Lp, pad, cx;
-  const Stencil* stencil;
-  const float2* cs32;
+  int L, R, T, S1, S, M, Lp, pad, cx, r_min;
+  const double2* cs64;
   const float2* G;       // [R][128]: (c - d, c + d) of the reference's weighted spectrum per slot
   int32_t *ref, *shift_x, *shift_y, *psi, *mirror, *flat;
   float *cc, *cc2;

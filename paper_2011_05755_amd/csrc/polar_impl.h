@@ -18,11 +18,71 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// (cos, sin)(2 pi j / 256) as float-float pairs, cos = ch + cl and
+// sin = sh + sl, staged in LDS: the resampling positions and, through
+// (ch, sh), the ring FFT twiddles.
+struct __attribute__((aligned(16))) CosSin {
+  float ch, sh, cl, sl;
+};
+
+__device__ __forceinline__ void stage_cs(CosSin* t, const double2* cs64) {
+  for (int j = threadIdx.x; j < kNphi; j += blockDim.x) {
+    const double2 v = cs64[j];
+    CosSin c;
+    c.ch = (float)v.x;
+    c.sh = (float)v.y;
+    c.cl = (float)(v.x - (double)c.ch);
+    c.sl = (float)(v.y - (double)c.sh);
+    t[j] = c;
+  }
+}
+
+// exp(-2 pi i e / 256) from the staged table
+__device__ __forceinline__ float2 twid(const CosSin* t, int e) {
+  const float2 v = *reinterpret_cast<const float2*>(t + e);
+  return make_float2(v.x, -v.y);
+}
+
 __device__ __forceinline__ void stage_image(float* img, const float* src, int L, int Lp, int pad) {
   for (int i = threadIdx.x; i < Lp * Lp; i += blockDim.x) {
     const int yy = i / Lp - pad, xx = i % Lp - pad;
     img[i] = (yy >= 0 && yy < L && xx >= 0 && xx < L) ? src[yy * L + xx] : 0.f;
   }
+}
+
+// The same taps for a byte offset o4 of the top-left pixel and the row pitch
+// Lp4 in bytes.
+__device__ __forceinline__ float bilin4(const float* img, int o4, int Lp4, float fx, float fy) {
+  const char* p = reinterpret_cast<const char*>(img) + o4;
+  const float i00 = *reinterpret_cast<const float*>(p), i10 = *reinterpret_cast<const float*>(p + 4);
+  const float i01 = *reinterpret_cast<const float*>(p + Lp4), i11 = *reinterpret_cast<const float*>(p + Lp4 + 4);
+  const float top = i00 + fx * (i10 - i00);
+  const float bot = i01 + fx * (i11 - i01);
+  return top + fy * (bot - top);
+}
+
+// Offset (in pixels) of integer shift s = sy_index * S1 + sx_index, both
+// indices counted from -T, for an image of pitch Lp: (sy - T) Lp + (sx - T).
+// s / S1 is taken as (s * m) >> 16 with m = ceil(65536 / S1), which is exact
+// for 0 <= s < 65536 / S1 (here s < 289 and S1 <= 17).
+__device__ __forceinline__ int shift_offset(int s, int S1, int m, int T, int Lp) {
+  const int q = __mul24(s, m) >> 16;
+  return __mul24(q, Lp - S1) + s - T * (Lp + 1);
+}
+
+// Bilinear sample of the staged image at offset rr (cos, sin) of angle entry
+// c from the pixel at byte offset o4 (centre plus shift).  Floor and
+// fractions come from the float-float cos/sin: each fraction is within a
+// few FP32 ulps of the one the FP64 position gives.  Where the position lies
+// within rounding of a pixel boundary, floor(rr * ch) can be one off the
+// exact floor; the fraction is then just outside [0, 1), the sample is the
+// same up to rounding, and the taps reach one pixel further, which the zero
+// border of the staged image allows for.
+__device__ __forceinline__ float polar_tap(const float* img, int o4, int Lp4, float rr, const CosSin& c) {
+  const float xf = floorf(rr * c.ch), yf = floorf(rr * c.sh);
+  const float fx = fmaf(rr, c.cl, fmaf(rr, c.ch, -xf));
+  const float fy = fmaf(rr, c.sl, fmaf(rr, c.sh, -yf));
+  return bilin4(img, o4 + __mul24((int)yf, Lp4) + 4 * (int)xf, Lp4, fx, fy);
 }
 
 __device__ __forceinline__ float bilin(const float* img, int o, int Lp, float fx, float fy) {
