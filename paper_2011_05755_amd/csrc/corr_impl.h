@@ -76,15 +76,17 @@ struct Op16<kFP16> {
 };
 
 // Particle operand of lane ln for slot `slot`: ring g*R4 + t of lane group
-// g = ln/16 at element t * kRingStride (A layout [tile][ring][slot][16],
-// the slot at slot_pos(slot) for the FP32 contraction, PERM).  Rings >= R
-// are padding that the polar kernel never writes: callers mask them.
+// g = ln/16 at element t * ring_stride(LAYOUT) (ALayout, fixed per
+// contraction form; the host has the resampler write the same one).  Rings
+// >= R are padding that the polar kernel never writes: callers mask them.
 // RX > 0: R4 == RX is known at compile time.
-constexpr int kRingStride = kSlots * 16;
-template <int RX = 0, bool PERM = false>
+constexpr int ring_stride(int layout) { return layout == kSlotMajor ? 16 : kSlots * 16; }
+template <int LAYOUT, int RX = 0>
 __device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int slot, int ln) {
   const int R4 = RX > 0 ? RX : a.R4;
-  const int pos = PERM ? slot_pos(slot) : slot;
+  if constexpr (LAYOUT == kSlotMajor)
+    return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
+  const int pos = LAYOUT == kRingPerm ? slot_pos(slot) : slot;
   return a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + pos) * 16 + (ln & 15);
 }
 // Element t of the lane's operand: ring (ln/16)*R4 + t.  The load is never
@@ -93,11 +95,11 @@ __device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int 
 // t >= R4 and padding rings >= R (which hold no data) are cleared by an AND
 // with a mask that is opaque to the optimiser, which would otherwise turn
 // the select back into a branch around the load.
-template <int RX = 0>
+template <int LAYOUT, int RX = 0>
 __device__ __forceinline__ float a_elem(const CorrArgs& a, const float* ap, int ln, int t, bool nt) {
   const int R4 = RX > 0 ? RX : a.R4;
   const int tt = t < R4 ? t : R4 - 1;
-  const float x = nt ? __builtin_nontemporal_load(ap + tt * kRingStride) : ap[tt * kRingStride];
+  const float x = nt ? __builtin_nontemporal_load(ap + tt * ring_stride(LAYOUT)) : ap[tt * ring_stride(LAYOUT)];
   uint32_t keep = (t < R4 && (ln >> 4) * R4 + t < a.R) ? 0xffffffffu : 0u;
   asm("" : "+v"(keep));
   return __uint_as_float(__float_as_uint(x) & keep);
@@ -135,6 +137,7 @@ template <int NW, int MAXR, bool RES, bool EXACT>
 struct Fp32Contract {
   static constexpr int SPW = kSlots / NW;
   static constexpr int RX = EXACT ? MAXR : 0;
+  static constexpr int LAYOUT = (NW == 8 && RES) ? kRingPerm : kSlotMajor;
   float areg[RES ? SPW : 1][RES ? MAXR : 1];
   float e[4];  // high-slot energy of the lane's entries (store_block)
 
@@ -142,9 +145,9 @@ struct Fp32Contract {
     if constexpr (RES) {
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
-        const float* ap = a_lane<RX, true>(a, tile, w + NW * i, ln);
+        const float* ap = a_lane<LAYOUT, RX>(a, tile, w + NW * i, ln);
 #pragma unroll
-        for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<RX>(a, ap, ln, t, true);
+        for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<LAYOUT, RX>(a, ap, ln, t, true);
       }
     }
   }
@@ -187,9 +190,9 @@ struct Fp32Contract {
       // that the slot loop need not be unrolled)
       float b0[MAXR], a0[MAXR], b1[MAXR], a1[MAXR];
       auto loada = [&](int i, float (&dst)[MAXR]) {
-        const float* ap = a_lane<RX, true>(a, tile, w + NW * i, ln);
+        const float* ap = a_lane<LAYOUT, RX>(a, tile, w + NW * i, ln);
 #pragma unroll
-        for (int t = 0; t < MAXR; ++t) dst[t] = a_elem<RX>(a, ap, ln, t, false);
+        for (int t = 0; t < MAXR; ++t) dst[t] = a_elem<LAYOUT, RX>(a, ap, ln, t, false);
       };
       auto chain = [&](const float (&x)[MAXR], const float (&y)[MAXR], int slot) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -231,9 +234,9 @@ struct Half16Contract {
   float e[4];  // high-slot energy of the lane's entries (store_block)
 
   __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, float (&v)[8 * NS], bool nt) {
-    const float* ap = a_lane(a, tile, slot, ln);
+    const float* ap = a_lane<kRingMajor>(a, tile, slot, ln);
 #pragma unroll
-    for (int t = 0; t < 8 * NS; ++t) v[t] = t < MAXR ? a_elem(a, ap, ln, t, nt) : 0.f;
+    for (int t = 0; t < 8 * NS; ++t) v[t] = t < MAXR ? a_elem<kRingMajor>(a, ap, ln, t, nt) : 0.f;
   }
   __device__ __forceinline__ void pack(const float (&v)[8 * NS], u32x4 (&dst)[NS]) const {
 #pragma unroll

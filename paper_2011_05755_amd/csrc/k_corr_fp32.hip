@@ -26,9 +26,10 @@ void corr_dispatch_fp32(int variant, int r4min, int r4max, const CorrArgs* a, bo
   return go(Cfg<kFP32, 8, 16, false, false>{});
 }
 
-// runner-up pass: particle operand resident (run-time R4 <= 9), else streamed
+// runner-up pass over the operand the first pass read: resident when that was
+// the 8-wave resident form's layout (R4 <= 9), else streamed (slot-major)
 void corr_runner_up_fp32(const CorrArgs& a, hipStream_t st) {
-  if (a.R4 <= 9) launch_mode<Cfg<kFP32, 8, 9, true, false>, kRunnerUp>(a, st);
+  if (a.a_layout == kRingPerm) launch_mode<Cfg<kFP32, 8, 9, true, false>, kRunnerUp>(a, st);
   else launch_mode<Cfg<kFP32, 8, 16, false, false>, kRunnerUp>(a, st);
 }
 

@@ -142,16 +142,18 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       const int tile = q0 + grp;
       const int first = row0 - tile * 8;            // rows of this tile before the particle
       const int last = row0 + a.S - tile * 8;       // first row after the particle
-      float* dst = a.out + ((size_t)tile * 4 * a.R4 + ring) * kSlots * 16;
+      // the lane's segment of slot s = 64 h + 16 it + j (j = lane / 4): slot
+      // stride ss; position s, or slot_pos(s) = (j & 7) * 16 + (j >> 3) + 8 h
+      // + 2 it; a per-lane part computed once per item and a uniform offset
+      const bool slot_major = a.a_layout == kSlotMajor, perm = a.a_layout == kRingPerm;
+      const int ss = slot_major ? a.R4 * 64 : 16;
+      float* dst = a.out + (slot_major ? (size_t)tile * kSlots * a.R4 * 64 + ring * 16
+                                       : ((size_t)tile * 4 * a.R4 + ring) * kSlots * 16);
       const int part = lnx & 3;                       // rows (part & 1) * 4 .. +3 of p = part >> 1
       const int r0 = (part & 1) * 4;
       const bool full = r0 >= first && r0 + 4 <= last;
-      // the lane's segment of slot s = 64 h + 16 it + j (j = lane / 4) sits at
-      // s, or at slot_pos(s) = (j & 7) * 16 + (j >> 3) + 8 h + 2 it: a
-      // per-lane part computed once per item and a uniform offset
       const int j = lnx >> 2;
-      const bool perm = a.slot_perm != 0;
-      float* const lane_dst = dst + (perm ? (j & 7) * 16 + (j >> 3) : j) * 16 + part * 4;
+      float* const lane_dst = dst + (size_t)__mul24(perm ? (j & 7) * 16 + (j >> 3) : j, ss) + part * 4;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -166,7 +168,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         for (int it = 0; it < 4; ++it) {
           const int sl = it * 16 + (lnx >> 2);
           const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
-          float* o = lane_dst + (perm ? 8 * h + 2 * it : 64 * h + 16 * it) * 16;
+          float* o = lane_dst + (size_t)(perm ? 8 * h + 2 * it : 64 * h + 16 * it) * ss;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;
           } else {

@@ -82,11 +82,24 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
       const int sc = s < a.S ? s : a.S - 1;       // rows past the last shift repeat it (never chosen)
       const int o4 = 4 * (base + shift_offset(sc, a.S1, s1m, a.T, a.Lp));
 
-      const float rr = (float)(a.r_min + ring);
-      const CosSin* cp = cs + 2 * lx;
+      // 32 bilinear samples from the stencil table, read from the cache in
+      // two batches of 16 (this kernel is bound by its vector ALU work, so
+      // cached stencils beat positions computed in the loop)
+      const Stencil* sp = a.stencil + ring * kNphi + 2 * lx;
       float v[32];
 #pragma unroll
-      for (int i = 0; i < 32; ++i) v[i] = polar_tap(img, o4, Lp4, rr, cp[16 * (i >> 1) + (i & 1)]);
+      for (int h = 0; h < 2; ++h) {
+        Stencil st[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int i = 16 * h + j;
+          st[j] = sp[16 * (i >> 1) + (i & 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          v[16 * h + j] = bilin4(img, o4 + __mul24(st[j].dy, Lp4) + st[j].bx, Lp4, st[j].fx, st[j].fy);
+        __builtin_amdgcn_sched_barrier(0);
+      }
 
       float2 z[16];
 #pragma unroll

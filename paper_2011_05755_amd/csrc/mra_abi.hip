@@ -267,13 +267,14 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
   pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx;
   pa.r_min = rs.g.r_min;
-  pa.slot_perm = rs.g.precision == kFP32;
+  pa.a_layout = a_layout_for(rs.g.precision, table ? 2 : rs.variant);
   pa.cs64 = c->cs64;
   pa.out = A;
   timed(c, "polar", [&] { hip_check(c, launch_polar(0, pa, st), "polar"); });
 
   CorrArgs ca{};
   ca.A = A;
+  ca.a_layout = pa.a_layout;
   ca.n_row_tiles = tiles;
   ca.rows = rows;
   ca.B32 = rs.B32;
@@ -346,6 +347,7 @@ void run_single(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts,
     ra.out_off = n0;
     ra.L = L; ra.R = rs.R; ra.T = p.T; ra.S1 = p.S1; ra.S = p.S; ra.M = p.M;
     ra.Lp = p.Lp; ra.pad = p.pad; ra.cx = p.cx; ra.r_min = rs.g.r_min;
+    ra.stencil = rs.stencil;
     ra.cs64 = c->cs64;
     ra.G = rs.G1;
     ra.ref = out->ref; ra.shift_x = out->shift_x; ra.shift_y = out->shift_y;
@@ -439,11 +441,11 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     pa.parts = src; pa.n_part = pc.nc;
     pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = pc.p.T; pa.S1 = pc.p.S1; pa.S = pc.p.S;
     pa.Lp = pc.p.Lp; pa.pad = pc.p.pad; pa.cx = pc.p.cx; pa.r_min = rs.g.r_min; pa.cs64 = c->cs64; pa.out = Ap;
-    pa.slot_perm = rs.g.precision == kFP32;
+    pa.a_layout = a_layout_for(prec, variant);
     pb.start[i] = part;
 
     CorrArgs& ca = cb.piece[i];
-    ca.A = Ap; ca.n_row_tiles = ptiles; ca.rows = prow;
+    ca.A = Ap; ca.a_layout = pa.a_layout; ca.n_row_tiles = ptiles; ca.rows = prow;
     ca.B32 = rs.B32; ca.B16 = rs.B16;
     ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = pc.p.S; ca.M = pc.p.M;
     ca.maxabs = mx; ca.b_scale = rs.b_scale; ca.cs32 = c->cs32;

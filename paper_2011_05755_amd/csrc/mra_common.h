@@ -11,10 +11,6 @@ namespace mra {
 constexpr int kNphi = 256;          // angles per ring (the paper's workloads)
 constexpr int kSlots = 128;         // frequency slots: f = 1..127, slot 0 = (f 0, f 128)
 
-// Position of slot s within a ring of the particle operand of the FP32
-// contraction: the slots s = w + 8 i that wave w of the correlation kernel
-// contracts are contiguous.  (The 16-bit contractions read slot s at s.)
-__host__ __device__ constexpr int slot_pos(int s) { return (s & 7) * 16 + (s >> 3); }
 constexpr int kRowTile = 8;         // particle rows (shift, particle) per correlation tile
 constexpr int kRefTile = 8;         // references per correlation tile
 constexpr int kPolarWaves = 4;      // resampling workgroup: 4 waves, 8 shifts x 8 FFT lanes each
@@ -25,8 +21,24 @@ constexpr int kAvgThreads = 256;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
+// Layouts of the particle operand A (per row tile of 8 rows, 16 floats per
+// (ring, slot): p*8 + row%8):
+//   kRingMajor  [ring < 4*R4][slot][16]: one (ring, row group) item of the
+//               resampler writes one contiguous 8 KB run
+//   kRingPerm   the same with slot s at slot_pos(s), so that the slots
+//               s = w + 8 i of correlation wave w are contiguous (FP32,
+//               8 waves, operand resident)
+//   kSlotMajor  [slot][ring < 4*R4][16]: each slot's rings contiguous (FP32
+//               4-wave and streamed contractions, which re-read the operand)
+enum ALayout { kRingMajor = 0, kRingPerm = 1, kSlotMajor = 2 };
+__host__ __device__ constexpr int slot_pos(int s) { return (s & 7) * 16 + (s >> 3); }
+// The layout a correlation launch reads (and the resampler must write).
+__host__ __device__ constexpr int a_layout_for(int prec, int variant) {
+  return prec != kFP32 ? kRingMajor : (variant == 0 ? kRingPerm : kSlotMajor);
+}
+
 // Entry of the particle sampling stencil for ring r and angle j (FP64
-// positions, used by the FP32 re-score): the floor (dx, dy) of
+// positions, used by the FP32 re-score and the single-reference kernel): the floor (dx, dy) of
 // r*(cos, sin)(theta_j), stored as bx = 4 dx (the byte offset of the column
 // in a float row) and dy, and the bilinear fractions.
 struct __attribute__((aligned(16))) Stencil {
@@ -35,8 +47,7 @@ struct __attribute__((aligned(16))) Stencil {
 };
 
 // Resample + ring-FFT kernel.  out layout depends on the mode:
-//  mode 0: correlation operand A, [row tile][ring < 4*R4][slot][16] float
-//          (slot at slot_pos(slot) when slot_perm is set),
+//  mode 0: correlation operand A in layout a_layout (ALayout),
 //          inner index p*8 + row%8 (p = 0: a-b, p = 1: a+b); rings >= R are
 //          never written (the correlation kernel masks them)
 //  mode 1: polar samples [n][S][R][256]
@@ -47,14 +58,15 @@ struct PolarArgs {
   int L, R, R4, T, S1, S;
   int Lp, pad, cx;     // LDS image side (with zero border), border width, centre
   int r_min;           // radius of ring 0
-  int slot_perm;       // mode 0: slots at slot_pos (FP32 contraction) rather than in order
+  int a_layout;        // mode 0: ALayout of the operand
   const double2* cs64; // (cos, sin)(2 pi j / 256)
   float* out;
 };
 
 // Fused contraction + inverse FFT over angle + arg-max.
 struct CorrArgs {
-  const float* A;        // [row tiles][4*R4][128][16]
+  const float* A;        // [row tiles][...] in layout a_layout (ALayout)
+  int a_layout;
   int n_row_tiles;
   int rows;              // valid rows in the chunk (n * S)
   const float* B32;      // [ref tiles][128][R4][64]
@@ -135,6 +147,7 @@ struct RfaArgs {
   int n_part;
   int64_t out_off;
   int L, R, T, S1, S, M, Lp, pad, cx, r_min;
+  const Stencil* stencil;  // [R][256]
   const double2* cs64;
   const float2* G;       // [R][128]: (c - d, c + d) of the reference's weighted spectrum per slot
   int32_t *ref, *shift_x, *shift_y, *psi, *mirror, *flat;
