@@ -143,9 +143,12 @@ struct Fp32Contract {
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
+      // permuted layout: the wave's slots w + 8 i sit at positions 16 w + i,
+      // one base address and constant offsets
+      const float* a0 = LAYOUT == kRingPerm ? a_lane<LAYOUT, RX>(a, tile, w, ln) : nullptr;
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
-        const float* ap = a_lane<LAYOUT, RX>(a, tile, w + NW * i, ln);
+        const float* ap = LAYOUT == kRingPerm ? a0 + 16 * i : a_lane<LAYOUT, RX>(a, tile, w + NW * i, ln);
 #pragma unroll
         for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<LAYOUT, RX>(a, ap, ln, t, true);
       }
