@@ -105,6 +105,22 @@ __device__ __forceinline__ float a_elem(const CorrArgs& a, const float* ap, int 
   return __uint_as_float(__float_as_uint(x) & keep);
 }
 
+// Elements t of two slots at once in the permuted layout (kRingPerm): ap
+// points at element 0 of the lane's pair block; masks as in a_elem.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <int RX = 0>
+__device__ __forceinline__ f32x2 a_pair(const CorrArgs& a, const float* ap, int ln, int t) {
+  const int R4 = RX > 0 ? RX : a.R4;
+  const int tt = t < R4 ? t : R4 - 1;
+  const f32x2 x = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(ap + tt * kSlots * 16));
+  uint32_t keep = (t < R4 && (ln >> 4) * R4 + t < a.R) ? 0xffffffffu : 0u;
+  asm("" : "+v"(keep));
+  f32x2 r;
+  r.x = __uint_as_float(__float_as_uint(x.x) & keep);
+  r.y = __uint_as_float(__float_as_uint(x.y) & keep);
+  return r;
+}
+
 // Frequency slots below kLowSlots enter the pruning bound with their exact
 // magnitudes, the others through their summed energy.
 constexpr int kLowSlots = 32;
@@ -143,14 +159,28 @@ struct Fp32Contract {
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
-      // permuted layout: the wave's slots w + 8 i sit at positions 16 w + i,
-      // one base address and constant offsets
-      const float* a0 = LAYOUT == kRingPerm ? a_lane<LAYOUT, RX>(a, tile, w, ln) : nullptr;
+      if constexpr (LAYOUT == kRingPerm) {
+        // the wave's slots w + 8 i sit at positions 16 w + i, in pairs
+        // (i even, i + 1) interleaved by element: one base address, constant
+        // offsets, one 8-byte load for two slots
+        const int R4 = RX > 0 ? RX : a.R4;
+        const float* a0 = a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + 16 * w) * 16 + 2 * (ln & 15);
 #pragma unroll
-      for (int i = 0; i < SPW; ++i) {
-        const float* ap = LAYOUT == kRingPerm ? a0 + 16 * i : a_lane<LAYOUT, RX>(a, tile, w + NW * i, ln);
+        for (int i2 = 0; i2 < SPW / 2; ++i2) {
 #pragma unroll
-        for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<LAYOUT, RX>(a, ap, ln, t, true);
+          for (int t = 0; t < MAXR; ++t) {
+            const f32x2 v = a_pair<RX>(a, a0 + 32 * i2, ln, t);
+            areg[2 * i2][t] = v.x;
+            areg[2 * i2 + 1][t] = v.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) {
+          const float* ap = a_lane<LAYOUT, RX>(a, tile, w + NW * i, ln);
+#pragma unroll
+          for (int t = 0; t < MAXR; ++t) areg[i][t] = a_elem<LAYOUT, RX>(a, ap, ln, t, true);
+        }
       }
     }
   }

@@ -142,9 +142,9 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       const int tile = q0 + grp;
       const int first = row0 - tile * 8;            // rows of this tile before the particle
       const int last = row0 + a.S - tile * 8;       // first row after the particle
-      // the lane's segment of slot s = 64 h + 16 it + j (j = lane / 4): slot
-      // stride ss; position s, or slot_pos(s) = (j & 7) * 16 + (j >> 3) + 8 h
-      // + 2 it; a per-lane part computed once per item and a uniform offset
+      // otherwise the lane's segment of slot s = 64 h + 16 it + j (j = lane /
+      // 4), slot stride ss: a per-lane part computed once per item and a
+      // uniform offset
       const bool slot_major = a.a_layout == kSlotMajor, perm = a.a_layout == kRingPerm;
       const int ss = slot_major ? a.R4 * 64 : 16;
       float* dst = a.out + (slot_major ? (size_t)tile * kSlots * a.R4 * 64 + ring * 16
@@ -153,7 +153,15 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       const int r0 = (part & 1) * 4;
       const bool full = r0 >= first && r0 + 4 <= last;
       const int j = lnx >> 2;
-      float* const lane_dst = dst + (size_t)__mul24(perm ? (j & 7) * 16 + (j >> 3) : j, ss) + part * 4;
+      float* const lane_dst = dst + (size_t)__mul24(j, ss) + part * 4;
+      // kRingPerm: lane (pp = lane / 8, c = lane % 8) writes elements 2c, 2c+1
+      // (rows rp, rp + 1) of the position pair 16 it + 4 h + lp, whose slots
+      // are 64 h + sp and 64 h + sp + 8, interleaved by element
+      const int pp = lnx >> 3, c = lnx & 7;
+      const int lp = 8 * (pp >> 2) + (pp & 3), sp = (pp >> 2) + 16 * (pp & 3);
+      const int rp = 2 * (c & 3);
+      const bool full_p = rp >= first && rp + 2 <= last;
+      float* const pair_dst = dst + 32 * lp + 4 * c;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -166,9 +174,22 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
         wave_sync();
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
+          if (perm) {
+            const int s0 = 2 * it + sp, s1 = s0 + 8, sw = (s0 & 3) << 2;  // s1 & 3 == s0 & 3
+            const float2 v0 = *reinterpret_cast<const float2*>(stage + s0 * 16 + ((2 * c) ^ sw));
+            const float2 v1 = *reinterpret_cast<const float2*>(stage + s1 * 16 + ((2 * c) ^ sw));
+            float* o = pair_dst + 32 * (16 * it + 4 * h);
+            if (full_p) {
+              *reinterpret_cast<float4*>(o) = make_float4(v0.x, v1.x, v0.y, v1.y);
+            } else {
+              if (rp >= first && rp < last) { o[0] = v0.x; o[1] = v1.x; }
+              if (rp + 1 >= first && rp + 1 < last) { o[2] = v0.y; o[3] = v1.y; }
+            }
+            continue;
+          }
           const int sl = it * 16 + (lnx >> 2);
           const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
-          float* o = lane_dst + (size_t)(perm ? 8 * h + 2 * it : 64 * h + 16 * it) * ss;
+          float* o = lane_dst + (size_t)(64 * h + 16 * it) * ss;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;
           } else {

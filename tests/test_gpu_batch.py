@@ -103,11 +103,15 @@ def test_tile_variants_and_chunk_sizes_do_not_change_results(ctx, data, precisio
     rid = 400 + variants[-1] * 10 + len(precision)
     ctx.load_refs(rid, refs, r_min=1, r_max=L // 2 - 2, shift_max=T, precision=precision)
     want = ctx.align(rid, parts).to_numpy()
+    # the runner-up pass re-reads the particle operand in the layout the
+    # variant's first pass had written
+    want2 = ctx.align(rid, parts, with_cc2=True).to_numpy()
     for v in variants:
         for chunk in (0, 1, 4):
             ctx.set_tuning(rid, corr_variant=v, chunk_particles=chunk)
             assert ctx.get_tuning(rid) == (v, chunk)
             same(ctx.align(rid, parts).to_numpy(), want, f"variant {v} chunk {chunk}")
+            same(ctx.align(rid, parts, with_cc2=True).to_numpy(), want2, f"cc2, variant {v} chunk {chunk}")
             out = mra.AlignResult.empty(N, DEV)
             ctx.align_batch([(rid, parts, -1, out)])
             same(out.to_numpy(), want, f"batch, variant {v} chunk {chunk}")
