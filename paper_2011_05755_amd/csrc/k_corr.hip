@@ -30,7 +30,7 @@ static void dispatch(int prec, int variant, int r4min, int r4max, const CorrArgs
 
 hipError_t launch_corr(int prec, int variant, bool table, const CorrArgs& a, hipStream_t st) {
   if (a.n_row_tiles <= 0) return hipSuccess;
-  if (table) variant = prec == kFP32 ? 2 : 0;  // any R4
+  if (table) variant = prec == kFP32 ? 2 : 0;  // any R4 (the host writes the operand for this form)
   if (!corr_variant_ok(prec, variant, a.R4)) return hipErrorInvalidValue;
   dispatch(prec, variant, a.R4, a.R4, &a, table, nullptr, 0, st);
   return hipGetLastError();

@@ -267,7 +267,8 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = p.T; pa.S1 = p.S1; pa.S = p.S;
   pa.Lp = p.Lp; pa.pad = p.pad; pa.cx = p.cx;
   pa.r_min = rs.g.r_min;
-  pa.a_layout = a_layout_for(rs.g.precision, table ? 2 : rs.variant);
+  // the CC table is written by the form launch_corr picks for it
+  pa.a_layout = a_layout_for(rs.g.precision, table ? (rs.g.precision == kFP32 ? 2 : 0) : rs.variant);
   pa.cs64 = c->cs64;
   pa.out = A;
   timed(c, "polar", [&] { hip_check(c, launch_polar(0, pa, st), "polar"); });
