@@ -2,8 +2,9 @@
 // each shifted particle resampled to polar coordinates and transformed per
 // ring), the FP32 re-score of a winning candidate, and the per-particle max |pixel|.
 //
-// One 4-wave workgroup per particle (about 50 KB of LDS at L = 76, so three
-// workgroups share a CU).  The image is staged once in LDS with a zero
+// One 8-wave workgroup per particle (about 68 KB of LDS at L = 76, so two
+// workgroups share a CU: 16 waves, against 12 with three 4-wave groups, which
+// ran 10 % slower).  The image is staged once in LDS with a zero
 // border (coalesced HBM read), beside a float-float cos/sin table; the
 // (ring, 8-row group) items of the particle are split between the waves.
 // In an item, lane (l, row) takes the 32 samples p[16 n1 + 2l + e] of shift

@@ -25,6 +25,16 @@ namespace mra {
 
 namespace {
 
+// 4 waves per particle (the resampling kernel runs 8): the 64 accumulators
+// per lane leave room for two waves per SIMD, and 35 rings split evenly
+constexpr int kRfaWaves = 4;
+constexpr int kRfaThreads = 64 * kRfaWaves;
+
+size_t rfa_lds_bytes(int Lp) {
+  return (size_t)((Lp * Lp + 3) & ~3) * sizeof(float) + (size_t)kRfaWaves * 64 * 9 * sizeof(float2) +
+         (size_t)kNphi * sizeof(CosSin);
+}
+
 constexpr int kRowStride = 136;  // float4 per row of the summed spectra (128 slots, padded)
 
 struct Best {
@@ -47,11 +57,11 @@ __device__ __forceinline__ void take(Best& b, float v, int i, float s) {
 
 // 64 accumulators per lane on top of the resampler's registers: at most
 // 256 VGPRs, two waves per SIMD.
-__global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rfa(RfaArgs a) {
+__global__ __launch_bounds__(kRfaThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rfa(RfaArgs a) {
   extern __shared__ float smem[];
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
-  CosSin* cs = reinterpret_cast<CosSin*>(scr + kPolarWaves * 64 * 9);
+  CosSin* cs = reinterpret_cast<CosSin*>(scr + kRfaWaves * 64 * 9);
   float4* V = reinterpret_cast<float4*>(scr);     // summed spectra; aliases the scratch between groups
   const int n = blockIdx.x;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
@@ -71,7 +81,7 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
 
-    for (int ring = w; ring < a.R; ring += kPolarWaves) {
+    for (int ring = w; ring < a.R; ring += kRfaWaves) {
       // opaque lane indices: addresses are recomputed per ring instead of
       // being held in registers across the loop
       int lx = l, rx = rl;
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
     // fixed-order sum of the four waves' partial spectra: V[row][slot]
     int sl[16];
     emit_slots(l, sl);
-    for (int ww = 0; ww < kPolarWaves; ++ww) {
+    for (int ww = 0; ww < kRfaWaves; ++ww) {
       if (w == ww) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
@@ -202,16 +212,16 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
     take(best, ov, oi, os);
   }
   float* rv = reinterpret_cast<float*>(scr);
-  int* ri = reinterpret_cast<int*>(scr) + 2 * kPolarWaves;
+  int* ri = reinterpret_cast<int*>(scr) + 2 * kRfaWaves;
   if (ln == 0) {
     rv[w] = best.v;
-    rv[kPolarWaves + w] = best.s;
+    rv[kRfaWaves + w] = best.s;
     ri[w] = best.i;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    Best b{rv[0], ri[0], rv[kPolarWaves]};
-    for (int ww = 1; ww < kPolarWaves; ++ww) take(b, rv[ww], ri[ww], rv[kPolarWaves + ww]);
+    Best b{rv[0], ri[0], rv[kRfaWaves]};
+    for (int ww = 1; ww < kRfaWaves; ++ww) take(b, rv[ww], ri[ww], rv[kRfaWaves + ww]);
     const int64_t gi = a.out_off + n;
     int idx = b.i;
     float cc = b.v;
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(kPolarThreads) __attribute__((amdgpu_waves_per_eu(2
 
 hipError_t launch_rfa(const RfaArgs& a, hipStream_t st) {
   if (a.n_part <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rfa, dim3(a.n_part), dim3(kPolarThreads), polar_lds_bytes(a.Lp), st, a);
+  hipLaunchKernelGGL(k_rfa, dim3(a.n_part), dim3(kRfaThreads), rfa_lds_bytes(a.Lp), st, a);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@ constexpr int kSlots = 128;         // frequency slots: f = 1..127, slot 0 = (f 
 
 constexpr int kRowTile = 8;         // particle rows (shift, particle) per correlation tile
 constexpr int kRefTile = 8;         // references per correlation tile
-constexpr int kPolarWaves = 4;      // resampling workgroup: 4 waves, 8 shifts x 8 FFT lanes each
+constexpr int kPolarWaves = 8;      // resampling workgroup: 8 waves, 8 shifts x 8 FFT lanes each
 constexpr int kPolarThreads = 64 * kPolarWaves;
 constexpr int kMaxBatchPieces = 12; // stack pieces per batched launch (kernel-argument table)
 constexpr int kAvgChunk = 64;       // particles per partial class sum
