@@ -76,18 +76,19 @@ struct Op16<kFP16> {
 };
 
 // Particle operand of lane ln for slot `slot`: ring g*R4 + t of lane group
-// g = ln/16 at element t * ring_stride(LAYOUT) (ALayout, fixed per
-// contraction form; the host has the resampler write the same one).  Rings
-// >= R are padding that the polar kernel never writes: callers mask them.
+// g = ln/16 at element t * ring_stride(LAYOUT) (kRingMajor or kSlotMajor,
+// fixed per contraction form; the host has the resampler write the same
+// one; kRingPerm is read two slots at a time with a_pair).  Rings >= R are
+// padding that the polar kernel never writes: callers mask them.
 // RX > 0: R4 == RX is known at compile time.
 constexpr int ring_stride(int layout) { return layout == kSlotMajor ? 16 : kSlots * 16; }
 template <int LAYOUT, int RX = 0>
 __device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int slot, int ln) {
+  static_assert(LAYOUT != kRingPerm, "the paired layout is read with a_pair");
   const int R4 = RX > 0 ? RX : a.R4;
   if constexpr (LAYOUT == kSlotMajor)
     return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
-  const int pos = LAYOUT == kRingPerm ? slot_pos(slot) : slot;
-  return a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + pos) * 16 + (ln & 15);
+  return a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + slot) * 16 + (ln & 15);
 }
 // Element t of the lane's operand: ring (ln/16)*R4 + t.  The load is never
 // conditional (a conditional load waits for its data before the next one is

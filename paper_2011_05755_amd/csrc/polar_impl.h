@@ -7,11 +7,6 @@
 
 namespace mra {
 
-__device__ __forceinline__ float2 w256f(const float2* cs, int e) {
-  float2 c = cs[e & 255];
-  return make_float2(c.x, -c.y);  // exp(-2 pi i e / 256)
-}
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
