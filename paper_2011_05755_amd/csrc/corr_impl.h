@@ -255,10 +255,9 @@ struct Fp32Contract {
 
 // Contraction with 16-bit operands; NS = ceil(MAXR / 8) steps of 8 rings
 // per lane group, R4 <= MAXR (EXACT: every work item has ceil(R4 / 8) == NS).
-// RES: the particle operand (layout kRingPerm) is converted once per row
-// tile (scaled for FP16) and kept packed in registers, two values per dword;
-// otherwise it (layout kRingMajor) is re-read and converted per reference
-// tile, one slot ahead.
+// RES: the particle operand is converted once per row tile (scaled for
+// FP16) and kept packed in registers, two values per dword; otherwise it is
+// re-read and converted per reference tile, one slot ahead.
 template <int PREC, int NW, int MAXR, bool EXACT, bool RES>
 struct Half16Contract {
   static constexpr int SPW = kSlots / NW;
@@ -286,26 +285,11 @@ struct Half16Contract {
       // issue the loads of several slots before converting any of them, so
       // the memory latency is paid a few times per workgroup instead of per slot
       constexpr int kBatch = NS == 1 ? 8 : 4;
-      // permuted, paired layout (8 waves): the wave's slots w + 8 i sit at
-      // positions 16 w + i, pairs (i even, i + 1) interleaved by element
-      const int R4 = a.R4;
-      const float* a0 = a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + 16 * w) * 16 + 2 * (ln & 15);
 #pragma unroll
       for (int i0 = 0; i0 < SPW; i0 += kBatch) {
         float v[kBatch][8 * NS];
 #pragma unroll
-        for (int bb = 0; bb < kBatch; bb += 2) {
-#pragma unroll
-          for (int t = 0; t < 8 * NS; ++t) {
-            if (t < MAXR) {
-              const f32x2 p = a_pair(a, a0 + 16 * (i0 + bb), ln, t);
-              v[bb][t] = p.x;
-              v[bb + 1][t] = p.y;
-            } else {
-              v[bb][t] = v[bb + 1][t] = 0.f;
-            }
-          }
-        }
+        for (int bb = 0; bb < kBatch; ++bb) fetch(a, tile, w + NW * (i0 + bb), ln, v[bb], true);
 #pragma unroll
         for (int bb = 0; bb < kBatch; ++bb) pack(v[bb], areg[i0 + bb]);
       }

@@ -12,9 +12,7 @@ void corr_dispatch_fp16(int variant, int r4min, int r4max, const CorrArgs* a, bo
 }
 
 void corr_runner_up_fp16(const CorrArgs& a, hipStream_t st) {
-  // over the operand the first pass read: resident (permuted layout) or streamed
-  if (a.a_layout == kRingPerm) launch_mode<Cfg<kFP16, 8, 16, true, false>, kRunnerUp>(a, st);
-  else launch_mode<Cfg<kFP16, 8, 16, false, false>, kRunnerUp>(a, st);
+  launch_mode<Cfg<kFP16, 8, 16, true, false>, kRunnerUp>(a, st);  // operand resident, R4 <= 16
 }
 
 }  // namespace mra

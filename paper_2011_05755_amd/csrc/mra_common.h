@@ -24,20 +24,20 @@ enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 // Layouts of the particle operand A (per row tile of 8 rows, 16 floats per
 // (ring, slot): p*8 + row%8):
 //   kRingMajor  [ring < 4*R4][slot][16]: one (ring, row group) item of the
-//               resampler writes one contiguous 8 KB run (16-bit, streamed)
+//               resampler writes one contiguous 8 KB run
 //   kRingPerm   the same with slot s at position slot_pos(s), so that the
 //               slots s = w + 8 i of correlation wave w are contiguous, and
 //               positions 2m, 2m+1 interleaved element by element in one
 //               128-byte block (float 2k + (pos & 1) holds element k), so
-//               that one 8-byte load per lane reads both (8 waves, operand
-//               resident: FP32 and 16-bit)
+//               that one 8-byte load per lane reads both (FP32, 8 waves,
+//               operand resident)
 //   kSlotMajor  [slot][ring < 4*R4][16]: each slot's rings contiguous (FP32
 //               4-wave and streamed contractions, which re-read the operand)
 enum ALayout { kRingMajor = 0, kRingPerm = 1, kSlotMajor = 2 };
 __host__ __device__ constexpr int slot_pos(int s) { return (s & 7) * 16 + (s >> 3); }
 // The layout a correlation launch reads (and the resampler must write).
 __host__ __device__ constexpr int a_layout_for(int prec, int variant) {
-  return variant == 0 ? kRingPerm : (prec != kFP32 ? kRingMajor : kSlotMajor);
+  return prec != kFP32 ? kRingMajor : (variant == 0 ? kRingPerm : kSlotMajor);
 }
 
 // Entry of the particle sampling stencil for ring r and angle j (FP64
