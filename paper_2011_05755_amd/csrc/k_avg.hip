@@ -7,7 +7,8 @@
 //   1. per block of 1024 particles, per-class counts;
 //   2. one workgroup scans them into stable class offsets and splits every
 //      class into chunks of at most kAvgChunk particles;
-//   3. particles are scattered into class order (stable);
+//   3. particles are scattered into class order (stable; one wave per block
+//      of 1024 particles);
 //   4. one workgroup per chunk stages each image in LDS (coalesced read),
 //      warps it and accumulates in FP64 registers;
 //   5. per class and pixel the chunk sums are added in chunk order and
@@ -60,16 +61,40 @@ __global__ __launch_bounds__(256) void k_avg_scan(AvgArgs a) {
     for (int b = 0; b < a.n_blk; ++b) a.blk_off[(size_t)b * a.K + k] += a.cls_start[k];
 }
 
-__global__ void k_avg_scatter(AvgArgs a) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= a.n_blk) return;
-  int* off = a.blk_off + (size_t)b * a.K;
+// One wave per block of kAvgBlk particles, 64 at a time in particle order:
+// the lanes of one class take consecutive places (ballot, rank by mbcnt)
+// and the class's next place, kept in LDS, advances by their count, so each
+// class's list stays in ascending particle order.
+__global__ __launch_bounds__(64) void k_avg_scatter(AvgArgs a) {
+  extern __shared__ int off[];
+  const int b = blockIdx.x;
+  for (int k = threadIdx.x; k < a.K; k += 64) off[k] = a.blk_off[(size_t)b * a.K + k];
+  __syncthreads();
   const int64_t n0 = (int64_t)b * kAvgBlk;
-  for (int i = 0; i < kAvgBlk; ++i) {
-    const int64_t n = n0 + i;
-    if (n >= a.N) break;
-    const int k = a.ref[n];
-    if (k >= 0 && k < a.K) a.order[off[k]++] = (int)n;
+  for (int j = 0; j < kAvgBlk; j += 64) {
+    const int64_t n = n0 + j + threadIdx.x;
+    int k = -1;
+    if (n < a.N) {
+      const int kk = a.ref[n];
+      if (kk >= 0 && kk < a.K) k = kk;
+    }
+    uint64_t todo = __ballot(k >= 0);
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const int kk = __shfl(k, leader);
+      const uint64_t same = __ballot(k == kk);
+      const int base = off[kk];
+      if (k == kk) {
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0));
+        a.order[base + rank] = (int)n;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if ((int)threadIdx.x == leader) off[kk] = base + __popcll(same);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      todo &= ~same;
+    }
   }
 }
 
@@ -88,6 +113,12 @@ __global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
   int end = start + kAvgChunk;
   if (end > a.cls_start[k + 1]) end = a.cls_start[k + 1];
   const int L = a.L, L2 = L * L;
+  // the image sits in LDS with a zero border, one pixel before and two after
+  // each row and column: positions clamped to [-1, L] then need no bounds
+  // tests (a clamped position lands on border taps, as zero as the pixels
+  // outside the box, and inside the box nothing changes)
+  const int Lb = L + 3;
+  for (int i = threadIdx.x; i < Lb * Lb; i += kAvgThreads) img[i] = 0.f;
   // each thread's pixels u = tid + i * kAvgThreads; the next particle's
   // pixels are loaded into registers while the current one is warped
   float nxt[PPT];
@@ -99,6 +130,15 @@ __global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
       nxt[i] = u < L2 ? __builtin_nontemporal_load(src + u) : 0.f;
     }
   };
+  // (row << 16) | column of the thread's pixels, kept packed; the values
+  // derived from them are recomputed per particle (made opaque below)
+  // rather than held in registers across the particle loop
+  uint32_t rc[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int u = threadIdx.x + i * kAvgThreads;
+    rc[i] = u < L2 ? ((uint32_t)(u / L) << 16) | (uint32_t)(u % L) : 0xffffffffu;
+  }
   double acc[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) acc[i] = 0.0;
@@ -108,8 +148,9 @@ __global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
     __syncthreads();  // the previous particle's warp has finished reading img
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int u = threadIdx.x + i * kAvgThreads;
-      if (u < L2) img[u] = nxt[i];
+      uint32_t r = rc[i];
+      asm volatile("" : "+v"(r));
+      if (r != 0xffffffffu) img[((int)(r >> 16) + 1) * Lb + (int)(r & 0xffffu) + 1] = nxt[i];
     }
     __syncthreads();
     if (pi + 1 < end) fetch(pi + 1);
@@ -121,20 +162,16 @@ __global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
     const float msign = a.mirror[n] ? -1.f : 1.f;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int u = threadIdx.x + i * kAvgThreads;
-      if (u < L2) {
-        const float vx = (float)(u % L - a.cx), vy = (float)(u / L - a.cx);
-        const float X = ox + (cs * vx - sn * vy);
-        const float Y = oy + msign * (sn * vx + cs * vy);
+      uint32_t r = rc[i];
+      asm volatile("" : "+v"(r));
+      if (r != 0xffffffffu) {
+        const float vx = (float)((int)(r & 0xffffu) - a.cx), vy = (float)((int)(r >> 16) - a.cx);
+        const float X = fminf(fmaxf(ox + (cs * vx - sn * vy), -1.f), (float)L);
+        const float Y = fminf(fmaxf(oy + msign * (sn * vx + cs * vy), -1.f), (float)L);
         const float x0 = floorf(X), y0 = floorf(Y);
         const float fx = X - x0, fy = Y - y0;
-        const int ix = (int)x0, iy = (int)y0;
-        const bool in_x0 = ix >= 0 && ix < L, in_x1 = ix + 1 >= 0 && ix + 1 < L;
-        const bool in_y0 = iy >= 0 && iy < L, in_y1 = iy + 1 >= 0 && iy + 1 < L;
-        const float i00 = (in_x0 && in_y0) ? img[iy * L + ix] : 0.f;
-        const float i10 = (in_x1 && in_y0) ? img[iy * L + ix + 1] : 0.f;
-        const float i01 = (in_x0 && in_y1) ? img[(iy + 1) * L + ix] : 0.f;
-        const float i11 = (in_x1 && in_y1) ? img[(iy + 1) * L + ix + 1] : 0.f;
+        const int o = ((int)y0 + 1) * Lb + (int)x0 + 1;
+        const float i00 = img[o], i10 = img[o + 1], i01 = img[o + Lb], i11 = img[o + Lb + 1];
         const float top = i00 + fx * (i10 - i00);
         const float bot = i01 + fx * (i11 - i01);
         acc[i] += (double)(top + fy * (bot - top));
@@ -165,9 +202,9 @@ hipError_t launch_averages(const AvgArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_avg_hist, dim3(a.n_blk), dim3(256), (size_t)a.K * sizeof(int), st, a);
   hipLaunchKernelGGL(k_avg_scan, dim3(1), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_avg_scatter, dim3((a.n_blk + 63) / 64), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(k_avg_scatter, dim3(a.n_blk), dim3(64), (size_t)a.K * sizeof(int), st, a);
   const int L2 = a.L * a.L;
-  const size_t lds = (size_t)L2 * sizeof(float);
+  const size_t lds = (size_t)(a.L + 3) * (a.L + 3) * sizeof(float);
   const int ppt = (L2 + kAvgThreads - 1) / kAvgThreads;
   dim3 g(a.max_chunks), b(kAvgThreads);
   if (ppt <= 16) hipLaunchKernelGGL(k_avg_accum<16>, g, b, lds, st, a);

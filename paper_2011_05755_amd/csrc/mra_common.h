@@ -16,7 +16,7 @@ constexpr int kRefTile = 8;         // references per correlation tile
 constexpr int kPolarWaves = 8;      // resampling workgroup: 8 waves, 8 shifts x 8 FFT lanes each
 constexpr int kPolarThreads = 64 * kPolarWaves;
 constexpr int kMaxBatchPieces = 12; // stack pieces per batched launch (kernel-argument table)
-constexpr int kAvgChunk = 64;       // particles per partial class sum
+constexpr int kAvgChunk = 32;       // particles per partial class sum
 constexpr int kAvgThreads = 256;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
