@@ -7,8 +7,8 @@
 //   1. per block of 1024 particles, per-class counts;
 //   2. one workgroup scans them into stable class offsets and splits every
 //      class into chunks of at most kAvgChunk particles;
-//   3. particles are scattered into class order (stable; one wave per block
-//      of 1024 particles);
+//   3. particles are scattered into class order (stable; one workgroup per
+//      block of 1024 particles);
 //   4. one workgroup per chunk stages each image in LDS (coalesced read),
 //      warps it and accumulates in FP64 registers;
 //   5. per class and pixel the chunk sums are added in chunk order and
@@ -35,33 +35,84 @@ __global__ __launch_bounds__(256) void k_avg_hist(AvgArgs a) {
   for (int k = threadIdx.x; k < a.K; k += 256) a.blk_cnt[(size_t)blockIdx.x * a.K + k] = hist[k];
 }
 
+// Per class: the total over blocks, then (one thread, K steps) the class and
+// chunk starts, then each block's offset = class start + earlier blocks'
+// counts.  The per-block loops carry no load-to-load dependence, so the
+// loads of several blocks are in flight at once.
 __global__ __launch_bounds__(256) void k_avg_scan(AvgArgs a) {
   for (int k = threadIdx.x; k < a.K; k += 256) {
     int run = 0;
-    for (int b = 0; b < a.n_blk; ++b) {
-      a.blk_off[(size_t)b * a.K + k] = run;
-      run += a.blk_cnt[(size_t)b * a.K + k];
-    }
+#pragma unroll 8
+    for (int b = 0; b < a.n_blk; ++b) run += a.blk_cnt[(size_t)b * a.K + k];
     a.counts[k] = run;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     int cs = 0, ch = 0;
     for (int k = 0; k < a.K; ++k) {
+      const int n = a.counts[k];
       a.cls_start[k] = cs;
       a.chunk_start[k] = ch;
-      cs += a.counts[k];
-      ch += (a.counts[k] + kAvgChunk - 1) / kAvgChunk;
+      cs += n;
+      ch += (n + kAvgChunk - 1) / kAvgChunk;
     }
     a.cls_start[a.K] = cs;
     a.chunk_start[a.K] = ch;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < a.K; k += 256)
-    for (int b = 0; b < a.n_blk; ++b) a.blk_off[(size_t)b * a.K + k] += a.cls_start[k];
+  for (int k = threadIdx.x; k < a.K; k += 256) {
+    int run = a.cls_start[k];
+#pragma unroll 8
+    for (int b = 0; b < a.n_blk; ++b) {
+      const int c = a.blk_cnt[(size_t)b * a.K + k];
+      a.blk_off[(size_t)b * a.K + k] = run;
+      run += c;
+    }
+  }
 }
 
-// One wave per block of kAvgBlk particles, 64 at a time in particle order:
+// One workgroup of 16 waves per block of kAvgBlk particles (K up to
+// kScatterMaxK): each wave ranks its 64 particles within their classes
+// (ballot, rank by mbcnt) and counts them per class in LDS; per class, the
+// waves' counts are turned into offsets in wave order after the block's own
+// offset; then every particle goes to offset + rank, so each class's list
+// stays in ascending particle order.
+constexpr int kScatterMaxK = 2048;  // 16 x K ints of LDS
+__global__ __launch_bounds__(1024) void k_avg_scatter16(AvgArgs a) {
+  extern __shared__ int cnt[];  // [16][K]
+  const int b = blockIdx.x, w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < 16 * a.K; i += 1024) cnt[i] = 0;
+  __syncthreads();
+  const int64_t n = (int64_t)b * kAvgBlk + threadIdx.x;
+  int k = -1;
+  if (n < a.N) {
+    const int kk = a.ref[n];
+    if (kk >= 0 && kk < a.K) k = kk;
+  }
+  int rank = 0;
+  uint64_t todo = __ballot(k >= 0);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int kk = __shfl(k, leader);
+    const uint64_t same = __ballot(k == kk);
+    if (k == kk) rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0));
+    if (ln == leader) cnt[w * a.K + kk] = __popcll(same);
+    todo &= ~same;
+  }
+  __syncthreads();
+  for (int kk = threadIdx.x; kk < a.K; kk += 1024) {
+    int run = a.blk_off[(size_t)b * a.K + kk];
+    for (int w2 = 0; w2 < 16; ++w2) {
+      const int c = cnt[w2 * a.K + kk];
+      cnt[w2 * a.K + kk] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  if (k >= 0) a.order[cnt[w * a.K + k] + rank] = (int)n;
+}
+
+// Larger K: one wave per block of kAvgBlk particles, 64 at a time in particle order:
 // the lanes of one class take consecutive places (ballot, rank by mbcnt)
 // and the class's next place, kept in LDS, advances by their count, so each
 // class's list stays in ascending particle order.
@@ -202,7 +253,10 @@ hipError_t launch_averages(const AvgArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_avg_hist, dim3(a.n_blk), dim3(256), (size_t)a.K * sizeof(int), st, a);
   hipLaunchKernelGGL(k_avg_scan, dim3(1), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_avg_scatter, dim3(a.n_blk), dim3(64), (size_t)a.K * sizeof(int), st, a);
+  if (a.K <= kScatterMaxK)
+    hipLaunchKernelGGL(k_avg_scatter16, dim3(a.n_blk), dim3(1024), (size_t)16 * a.K * sizeof(int), st, a);
+  else
+    hipLaunchKernelGGL(k_avg_scatter, dim3(a.n_blk), dim3(64), (size_t)a.K * sizeof(int), st, a);
   const int L2 = a.L * a.L;
   const size_t lds = (size_t)(a.L + 3) * (a.L + 3) * sizeof(float);
   const int ppt = (L2 + kAvgThreads - 1) / kAvgThreads;

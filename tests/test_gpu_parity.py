@@ -230,6 +230,33 @@ def test_averages_match_oracle_given_identical_parameters(ctx):
     assert torch.equal(avg, avg2)   # fixed summation order
 
 
+@pytest.mark.parametrize("K", [300, 2100])
+def test_averages_many_classes_and_blocks(ctx, K):
+    """More than one 1024-particle block of the class scatter, and K on both
+    sides of the scatter's LDS limit (16 K ints: one workgroup per block up
+    to K = 2048, one wave per block above)."""
+    log(f"class averages, K={K}")
+    from paper_2011_05755_amd import mra
+    L, T, N = 16, 1, 2500
+    refs, parts, _ = make_case(L, K, T, N, 0.1, 34)
+    ctx.load_refs(10, refs, r_min=1, r_max=L // 2 - 2, shift_max=T)
+    rng = np.random.default_rng(4)
+    ref = rng.integers(0, K, N)
+    params = dict(ref=ref, shift_x=rng.integers(-T, T + 1, N), shift_y=rng.integers(-T, T + 1, N),
+                  psi=rng.integers(0, 256, N), mirror=rng.integers(0, 2, N))
+    res = mra.AlignResult.empty(N, DEV)
+    for key, val in params.items():
+        getattr(res, key).copy_(torch.as_tensor(val, dtype=torch.int32))
+    avg = refs.clone()
+    counts = ctx.update_averages(10, parts, res, avg)
+    torch.cuda.synchronize()
+    want, cnt = oracle.averages(parts.cpu().numpy(), params, refs.cpu().numpy(), geom(L, L // 2 - 2, T))
+    np.testing.assert_array_equal(counts.cpu().numpy(), cnt)
+    err = np.abs(avg.cpu().numpy() - want).max() / np.abs(want).max()
+    assert err <= 1e-5, err
+    ctx.unload_refs(10)
+
+
 def test_batch_equals_individual_runs_and_runs_are_deterministic(ctx):
     log("align_batch vs individual")
     from paper_2011_05755_amd import mra
