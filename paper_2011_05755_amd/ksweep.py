@@ -1,0 +1,82 @@
+"""Multi-reference alignment time against the number of references.
+
+The paper times its MRA for several reference counts on 90 px particles with
+a search range of 3 and rings out to radius 36 (Sec. 5, Fig. 5a).  This sweep
+takes the same shapes on synthetic data: N particles of 90 px rendered from
+blob references (random rotation, integer shift within +-3, mirror with
+p = 0.5, SNR 0.05), rings 1..36 x 256 angles, K in --refs.  For every K and
+form, one alignment pass plus the class-average update is timed (wall clock
+over --reps passes after a warm-up, references resident), with the
+correlation kernel's own time from HIP events.  One JSON line per (K, form).
+
+    python -m paper_2011_05755_amd.ksweep --refs 10,20,50,100,200 --forms fp32,bf16
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+
+def log(msg):
+    print(f"[ksweep] {msg}", file=sys.stderr, flush=True)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--N", type=int, default=100000)
+    ap.add_argument("--refs", default="10,20,50,100,200")
+    ap.add_argument("--forms", default="fp32,bf16")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=12)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from . import mra, synth
+    dev = torch.device("cuda", 0)
+    L, r_min, r_max, T = 90, 1, 36, 3
+    Ks = [int(k) for k in args.refs.split(",") if k]
+    blobs = synth.make_blobs(max(Ks), L, seed=(args.seed, 0), rho_max=36.0)
+    refs_all = synth.render_refs(blobs).to(dev)
+    parts, _ = synth.make_particles(blobs, args.N, T, 0.05, seed=(args.seed, 1), device=dev)
+    torch.cuda.synchronize()
+    log(f"{args.N} particles of {L} px generated from {max(Ks)} references")
+
+    ctx = mra.Context(0)
+    rid = 0
+    for K in Ks:
+        refs = refs_all[:K].contiguous()
+        for form in args.forms.split(","):
+            rid += 1
+            ctx.load_refs(rid, refs, r_min=r_min, r_max=r_max, shift_max=T, precision=form)
+            out = mra.AlignResult.empty(args.N, dev)
+            avg = refs.clone()
+            ctx.align(rid, parts[:4096], out=out.narrow(0, 4096))   # warm-up
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(args.reps):
+                ctx.align(rid, parts, out=out)
+                ctx.update_averages(rid, parts, out, avg)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.reps
+            corr_ms, launches = ctx.profile_read("corr")
+            polar_ms, _ = ctx.profile_read("polar")
+            ctx.profile(False)
+            ctx.unload_refs(rid)
+            print(json.dumps(dict(
+                workload=f"MRA pass + average update: {args.N} particles, L={L}, K={K}, shifts +-{T} (49), "
+                         f"both mirrors, rings {r_min}..{r_max} x 256",
+                K=K, form=form, wall_s=round(wall, 4), particles_per_s=round(args.N / wall, 1),
+                corr_ms_per_pass=round(corr_ms / args.reps, 2), polar_ms_per_pass=round(polar_ms / args.reps, 2),
+                corr_launches_per_pass=launches // args.reps)), flush=True)
+            log(f"K={K} {form}: {wall * 1e3:.1f} ms per pass")
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
