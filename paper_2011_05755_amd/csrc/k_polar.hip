@@ -269,10 +269,12 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
 // pass and their neighbours one angle step either side; the best FP32 value
 // wins (ties: the smallest flat index) and replaces the parameters.
 constexpr int kMaxRescoreRows = 8;
+constexpr int kMaxRows = 289;  // shifts per particle at the largest search range (+-8)
 
 // FP32 CC of (ref k, shift soff, mirror m) at the lags lag0 + d, d < ND, for
-// the image staged in img; red holds ND x 256 doubles.  Reduction in a fixed
-// order (per-thread FP32 ring sum, then an FP64 tree), the same for every d.
+// the image staged in img; red holds 4 ND doubles.  Reduction in a fixed
+// order (per-thread FP32 ring sum, then FP64 across the block), the same for
+// every d.
 template <int ND>
 __device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* img, double* red, int k, int m,
                                              int soff, int lag0, double (&out)[ND]) {
@@ -283,6 +285,9 @@ __device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* 
   float acc[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) acc[d] = 0.f;
+  // unrolled so that the stencil and spectrum loads of several rings are in
+  // flight at once (the loop is bound by their latency, not by arithmetic)
+#pragma unroll 8
   for (int r = 0; r < a.R; ++r) {
     const Stencil st = a.stencil[r * kNphi + jj];
     const float p = bilin(img, base + st.dy * a.Lp + (st.bx >> 2) + soff, a.Lp, st.fx, st.fy);
@@ -290,25 +295,32 @@ __device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* 
 #pragma unroll
     for (int d = 0; d < ND; ++d) acc[d] += w * (p * q[r * kNphi + ((j + lag0 + d) & 255)]);
   }
+  // FP64 sum over the 256 threads in a fixed order: a butterfly within each
+  // wave (every lane ends with the wave's sum), then the four waves' sums in
+  // wave order
+  double v[ND];
 #pragma unroll
-  for (int d = 0; d < ND; ++d) red[d * 256 + j] = (double)acc[d];
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (j < h) {
+  for (int d = 0; d < ND; ++d) {
+    v[d] = (double)acc[d];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) red[d * 256 + j] += red[d * 256 + j + h];
-    }
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) v[d] += __shfl_xor(v[d], o);
   }
+  if ((j & 63) == 0) {
 #pragma unroll
-  for (int d = 0; d < ND; ++d) out[d] = red[d * 256];
+    for (int d = 0; d < ND; ++d) red[d * 4 + (j >> 6)] = v[d];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < ND; ++d) out[d] = ((red[d * 4] + red[d * 4 + 1]) + red[d * 4 + 2]) + red[d * 4 + 3];
   __syncthreads();
 }
 
 __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, float* smem) {
   float* img = smem;
   double* red = reinterpret_cast<double*>(smem + ((a.Lp * a.Lp + 1) & ~1));
-  int* cand = reinterpret_cast<int*>(red + 3 * 256);  // candidate rows' flat indices
+  int* cand = reinterpret_cast<int*>(red + 16);  // candidate rows' flat indices
+  float* rv = reinterpret_cast<float*>(cand + kMaxRescoreRows);  // the particle's row results
+  int* ri = reinterpret_cast<int*>(rv + kMaxRows);
   const int64_t gi = a.out_off + n;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
   if (a.rows <= 1) {
@@ -324,7 +336,13 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
     if (threadIdx.x == 0) a.cc[gi] = (float)v[0];
     return;
   }
-  // the a.rows best rows of the 16-bit pass (thread 0; S is at most 289)
+  // the a.rows best rows of the 16-bit pass (thread 0, from LDS; S is at
+  // most 289)
+  for (int s = threadIdx.x; s < a.S; s += 256) {
+    rv[s] = a.row_cc[(size_t)n * a.S + s];
+    ri[s] = a.row_idx[(size_t)n * a.S + s];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     float bv[kMaxRescoreRows];
     int bi[kMaxRescoreRows];
@@ -334,8 +352,8 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
       bi[i] = 0x7fffffff;
     }
     for (int s = 0; s < a.S; ++s) {
-      float v = a.row_cc[(size_t)n * a.S + s];
-      int i = a.row_idx[(size_t)n * a.S + s];
+      float v = rv[s];
+      int i = ri[s];
       if (i == 0x7fffffff) continue;
       for (int t = 0; t < nr; ++t)  // insertion into the sorted list
         if (v > bv[t] || (v == bv[t] && i < bi[t])) {
@@ -394,7 +412,8 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
 }
 
 static size_t rescore_lds_bytes(int Lp) {
-  return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + 3 * 256 * sizeof(double) + kMaxRescoreRows * sizeof(int);
+  return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + 16 * sizeof(double) + kMaxRescoreRows * sizeof(int) +
+         kMaxRows * (sizeof(float) + sizeof(int));
 }
 
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {

@@ -38,10 +38,24 @@ __device__ __forceinline__ float2 twid(const CosSin* t, int e) {
   return make_float2(v.x, -v.y);
 }
 
+// Batches of eight loads per thread are issued before any is stored, so the
+// HBM latency is paid once per batch rather than once per element.
 __device__ __forceinline__ void stage_image(float* img, const float* src, int L, int Lp, int pad) {
-  for (int i = threadIdx.x; i < Lp * Lp; i += blockDim.x) {
-    const int yy = i / Lp - pad, xx = i % Lp - pad;
-    img[i] = (yy >= 0 && yy < L && xx >= 0 && xx < L) ? src[yy * L + xx] : 0.f;
+  constexpr int kB = 8;
+  const int n = Lp * Lp;
+  for (int i0 = threadIdx.x; i0 < n; i0 += kB * blockDim.x) {
+    float v[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int i = i0 + b * blockDim.x;
+      const int yy = i / Lp - pad, xx = i % Lp - pad;
+      v[b] = (i < n && yy >= 0 && yy < L && xx >= 0 && xx < L) ? src[yy * L + xx] : 0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int i = i0 + b * blockDim.x;
+      if (i < n) img[i] = v[b];
+    }
   }
 }
 
