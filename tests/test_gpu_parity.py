@@ -81,6 +81,32 @@ def test_polar_samples(ctx, L, r_max, T):
         np.testing.assert_allclose(got[n], want, rtol=0, atol=2e-6 * np.abs(want).max())
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3)])
+def test_largest_geometry(ctx, precision, tol):
+    # the largest box, ring count and search range the C ABI admits: 160 px,
+    # rings 1..64 (R4 = 16), shifts +-8 (289 rows per mirror)
+    log(f"largest geometry L=160 r_max=64 T=8 {precision}")
+    L, r_max, T, K, N = 160, 64, 8, 3, 3
+    refs, parts, _ = make_case(L, K, T, N, 0.1, 47)
+    ctx.load_refs(36, refs, r_min=1, r_max=r_max, shift_max=T, precision=precision)
+    g = geom(L, r_max, T)
+    if precision == "fp32":
+        got = ctx.debug_polar(36, parts[:1]).cpu().numpy()
+        want = oracle.particle_polar(parts[0].cpu().numpy(), g)[0].reshape((2 * T + 1) ** 2, g.n_rings, 256)
+        np.testing.assert_allclose(got[0], want, rtol=0, atol=2e-6 * np.abs(want).max())
+    res = ctx.align(36, parts).to_numpy()
+    want = oracle.align(parts.cpu().numpy(), refs.cpu().numpy(), g)
+    err, _ = check_align(res, want, tol)
+    if precision != "fp32":   # the reported CC is the FP32 re-score of the chosen candidate
+        qhat, _ = oracle.reference_polar(refs.cpu().numpy(), g)
+        for n in range(N):
+            v = oracle.candidate_cc(parts[n].cpu().numpy(), qhat[res["ref"][n]], g, res["shift_x"][n],
+                                    res["shift_y"][n], res["mirror"][n], (256 - res["psi"][n]) % 256)
+            assert abs(res["cc"][n] - v) <= 1e-5 * abs(v), (n, res["cc"][n], v)
+    log(f"  max rel CC err {err:.2e}")
+    ctx.unload_refs(36)
+
+
 def test_ring_spectra_match_numpy_rfft_of_the_same_samples(ctx):
     log("ring spectra vs numpy rfft")
     L, T = 64, 2
