@@ -35,7 +35,7 @@ METRIC = "aligned particles/s (L=76,K=100,±3px); FP32 vs BF16-MFMA; p50/p99 lat
 FP32_MATRIX_PEAK = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 BF16_MATRIX_PEAK = 2500.0  # TFLOP/s, dense
 FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector (published; counts packed FP32)
-# reachable without packed FP32 (which this build disables): 256 CUs x 4 SIMDs
+# reachable without packed FP32 (which the library's compile flags disable): 256 CUs x 4 SIMDs
 # x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VALU_PEAK = 78.6
 HBM_PEAK = 8000.0          # GB/s
@@ -76,7 +76,7 @@ def main() -> int:
                          "a reference for hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described but not built", file=sys.stderr)
         return 2
 

@@ -70,7 +70,7 @@ typedef struct mra_ctx mra_ctx;
 /* Polar sampling geometry of a reference set.
  *  L          box size, 8 <= L <= 160
  *  r_min/max  1 <= r_min <= r_max <= 64 (integer ring radii)
- *  n_phi      angles per ring; this build supports 256 (the paper's
+ *  n_phi      angles per ring; the kernels support 256 (the paper's
  *             workloads); other values return MRA_E_INVAL
  *  shift_max  T >= 0: shifts {-T..T}^2 are searched (T <= 8)
  *  mirror     1: search the mirrored image too, 0: do not

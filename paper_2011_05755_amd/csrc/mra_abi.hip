@@ -162,7 +162,7 @@ void check_geom(const mra_geom* g) {
   if (!g) bad("geometry is NULL");
   if (g->L < 8 || g->L > 160) bad("L must be in [8, 160]");
   if (g->r_min < 1 || g->r_max < g->r_min || g->r_max > 64) bad("need 1 <= r_min <= r_max <= 64");
-  if (g->n_phi != kNphi) bad("n_phi must be 256 in this build");
+  if (g->n_phi != kNphi) bad("n_phi must be 256 (the only angular sampling the kernels implement)");
   if (g->shift_max < 0 || g->shift_max > 8) bad("shift_max must be in [0, 8]");
   if (g->mirror != 0 && g->mirror != 1) bad("mirror must be 0 or 1");
   if (g->precision < 0 || g->precision > 2) bad("precision must be MRA_FP32, MRA_BF16 or MRA_FP16");
