@@ -434,7 +434,7 @@ constexpr int kArgmax = 0, kTable = 1, kRunnerUp = 2;
 // pairs are packed into the lanes of each wave: a pass takes
 // ceil(CPW * live / 64) steps instead of CPW (CPW = 16 / NW columns or rows
 // per wave).  Results are identical with and without pruning.
-template <int PREC, int NW, class Contract, int MODE>
+template <int PREC, int NW, class Contract, int MODE, bool SPLIT>
 __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const CorrSmem<NW>& sm, Contract& con) {
   constexpr int CPW = 16 / NW;  // inverse-FFT columns (pass 1) and rows (pass 2) per wave
   const int tid = threadIdx.x, ln = tid & 63;
@@ -554,84 +554,180 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     __syncthreads();
 
     // ---------------- pass 2 + arg-max ----------------
-    {
-      const bool low = CPW * w < 8;  // wave-uniform
+    // Rows below 8 read upwards from slot 16 n1, the others downwards from
+    // slot 256 - 16 n1.  SPLIT: one loop per direction (each wave runs one),
+    // so that either keeps its 16 reads at constant offsets from one address
+    // (in one loop the compiler merges the two read sets into 31 per-element
+    // addresses); the kernels whose registers are full keep one loop.
+    if constexpr (SPLIT) {
+      {
+        auto pass2 = [&](auto dir_c) {
+        constexpr bool low = decltype(dir_c)::value == 1;  // 1 up, 2 down
 #pragma unroll 1
-      for (int n0 = 0; n0 < n_live; n0 += LPC) {
-        int lnx = ln;
-        asm volatile("" : "+v"(lnx));
-        const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
-        const bool act = n0 + lane_n < n_live;
-        const int P = list[act ? n0 + lane_n : 0];
-        const int row_l = P >> 3, ref_l = P & 7;
-        const int row = tile * kRowTile + row_l;
-        const int k = kt * kRefTile + ref_l;
-        float2 x[16];
-        if (low) {
-          const int base = n1 * 2048 + P;
+        for (int n0 = 0; n0 < n_live; n0 += LPC) {
+          int lnx = ln;
+          asm volatile("" : "+v"(lnx));
+          const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
+          const bool act = n0 + lane_n < n_live;
+          const int P = list[act ? n0 + lane_n : 0];
+          const int row_l = P >> 3, ref_l = P & 7;
+          const int row = tile * kRowTile + row_l;
+          const int k = kt * kRefTile + ref_l;
+          float2 x[16];
+          if constexpr (low) {
+            const int base = n1 * 2048 + P;
 #pragma unroll
-          for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
-        } else {
-          const int base = (513 - 32 * n1) * 64 + P;
-          x[0] = sm.stc[n1 == 8 ? 64 + P : base];
+            for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
+          } else {
+            const int base = (513 - 32 * n1) * 64 + P;  // k2 = 0; k2 steps go down by 128
+            int top = base - 15 * 128;                  // k2 = 15, the lowest address
+            asm volatile("" : "+v"(top));               // the base of the reads (not re-associated)
+            x[0] = sm.stc[n1 == 8 ? 64 + P : base];
 #pragma unroll
-          for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
-        }
-        inv_pass2(x);
-        if constexpr (MODE == kTable) {
-          if (act && row < a.rows && k < a.K) {
-            const int n = row / a.S, s = row - n * a.S;
-            const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
-            for (int m = 0; m < a.M; ++m) {
-              float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
-#pragma unroll
-              for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
-            }
+            for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[top + (15 - k2) * 128];
           }
-        } else {
-          // only values above the row's best of earlier reference tiles can
-          // win (a tie with an earlier tile loses: its flat index is smaller)
-          const float thr = sm.rb_v[row_l];
-          // the candidate left out of this pass (key m * 256 + angle of this
-          // lane's (row, ref)), or -1
-          int ex = -1;
-          if (MODE == kRunnerUp && row < a.rows && k < a.K) {
-            const int n = row / a.S, s = row - n * a.S;
-            const int e = a.excl[n];
-            if (e >= 0) {
-              const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
-              if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
-            }
-          }
-          float bv = -INFINITY;
-          int bi = 0x7fffffff;
-          float mx = -INFINITY;
+          inv_pass2(x);
+          if constexpr (MODE == kTable) {
+            if (act && row < a.rows && k < a.K) {
+              const int n = row / a.S, s = row - n * a.S;
+              const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
+              for (int m = 0; m < a.M; ++m) {
+                float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
 #pragma unroll
-          for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
-          if (MODE == kArgmax && mx > thr) {
-            // the lane's best is mx; its key is the smallest among the
-            // candidates equal to it (keys grow with n2, mirror 1 after 0)
-            bv = mx;
-            if (a.M == 2) {
-#pragma unroll
-              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
-            }
-#pragma unroll
-            for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
-          } else if (MODE == kRunnerUp && mx > thr) {
-#pragma unroll
-            for (int n2 = 0; n2 < 16; ++n2) {
-              const int ang = n1 + 16 * n2;
-              if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
-              if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
-                bv = x[n2].y;
-                bi = 256 + ang;
+                for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
               }
             }
+          } else {
+            // only values above the row's best of earlier reference tiles can
+            // win (a tie with an earlier tile loses: its flat index is smaller)
+            const float thr = sm.rb_v[row_l];
+            // the candidate left out of this pass (key m * 256 + angle of this
+            // lane's (row, ref)), or -1
+            int ex = -1;
+            if (MODE == kRunnerUp && row < a.rows && k < a.K) {
+              const int n = row / a.S, s = row - n * a.S;
+              const int e = a.excl[n];
+              if (e >= 0) {
+                const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
+                if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
+              }
+            }
+            float bv = -INFINITY;
+            int bi = 0x7fffffff;
+            float mx = -INFINITY;
+#pragma unroll
+            for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
+            if (MODE == kArgmax && mx > thr) {
+              // the lane's best is mx; its key is the smallest among the
+              // candidates equal to it (keys grow with n2, mirror 1 after 0)
+              bv = mx;
+              if (a.M == 2) {
+#pragma unroll
+                for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
+              }
+#pragma unroll
+              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
+            } else if (MODE == kRunnerUp && mx > thr) {
+#pragma unroll
+              for (int n2 = 0; n2 < 16; ++n2) {
+                const int ang = n1 + 16 * n2;
+                if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+                if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
+                  bv = x[n2].y;
+                  bi = 256 + ang;
+                }
+              }
+            }
+            if (act) {
+              sm.cand_v[(w * CPW + c) * 64 + P] = bv;
+              sm.cand_i[(w * CPW + c) * 64 + P] = bi;
+            }
           }
-          if (act) {
-            sm.cand_v[(w * CPW + c) * 64 + P] = bv;
-            sm.cand_i[(w * CPW + c) * 64 + P] = bi;
+        }
+        };
+        if (CPW * w < 8) pass2(std::integral_constant<int, 1>{});  // wave-uniform
+        else pass2(std::integral_constant<int, 2>{});
+      }
+    } else {
+      {
+        const bool low = CPW * w < 8;  // wave-uniform
+#pragma unroll 1
+        for (int n0 = 0; n0 < n_live; n0 += LPC) {
+          int lnx = ln;
+          asm volatile("" : "+v"(lnx));
+          const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
+          const bool act = n0 + lane_n < n_live;
+          const int P = list[act ? n0 + lane_n : 0];
+          const int row_l = P >> 3, ref_l = P & 7;
+          const int row = tile * kRowTile + row_l;
+          const int k = kt * kRefTile + ref_l;
+          float2 x[16];
+          if (low) {
+            const int base = n1 * 2048 + P;
+#pragma unroll
+            for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
+          } else {
+            const int base = (513 - 32 * n1) * 64 + P;
+            x[0] = sm.stc[n1 == 8 ? 64 + P : base];
+#pragma unroll
+            for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
+          }
+          inv_pass2(x);
+          if constexpr (MODE == kTable) {
+            if (act && row < a.rows && k < a.K) {
+              const int n = row / a.S, s = row - n * a.S;
+              const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
+              for (int m = 0; m < a.M; ++m) {
+                float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
+#pragma unroll
+                for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
+              }
+            }
+          } else {
+            // only values above the row's best of earlier reference tiles can
+            // win (a tie with an earlier tile loses: its flat index is smaller)
+            const float thr = sm.rb_v[row_l];
+            // the candidate left out of this pass (key m * 256 + angle of this
+            // lane's (row, ref)), or -1
+            int ex = -1;
+            if (MODE == kRunnerUp && row < a.rows && k < a.K) {
+              const int n = row / a.S, s = row - n * a.S;
+              const int e = a.excl[n];
+              if (e >= 0) {
+                const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
+                if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
+              }
+            }
+            float bv = -INFINITY;
+            int bi = 0x7fffffff;
+            float mx = -INFINITY;
+#pragma unroll
+            for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
+            if (MODE == kArgmax && mx > thr) {
+              // the lane's best is mx; its key is the smallest among the
+              // candidates equal to it (keys grow with n2, mirror 1 after 0)
+              bv = mx;
+              if (a.M == 2) {
+#pragma unroll
+                for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
+              }
+#pragma unroll
+              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
+            } else if (MODE == kRunnerUp && mx > thr) {
+#pragma unroll
+              for (int n2 = 0; n2 < 16; ++n2) {
+                const int ang = n1 + 16 * n2;
+                if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+                if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
+                  bv = x[n2].y;
+                  bi = 256 + ang;
+                }
+              }
+            }
+            if (act) {
+              sm.cand_v[(w * CPW + c) * 64 + P] = bv;
+              sm.cand_i[(w * CPW + c) * 64 + P] = bi;
+            }
           }
         }
       }
@@ -704,7 +800,7 @@ __global__ __launch_bounds__(NW * 64) void k_corr(CorrArgs a) {
   CorrSmem<NW> sm(smem);
   if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(a.cs32, threadIdx.x);
   typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
-  corr_tile<PREC, NW, decltype(con), MODE>(a, blockIdx.x, sm, con);
+  corr_tile<PREC, NW, decltype(con), MODE, NW == 8>(a, blockIdx.x, sm, con);
 }
 
 // Persistent form over the row tiles of several stacks.  Workgroup g takes
@@ -725,7 +821,7 @@ __global__ __launch_bounds__(NW * 64) void k_corr_batch(CorrBatch b) {
     if (threadIdx.x == 0) next = atomicAdd(b.counter, 1) + (int)gridDim.x;
     int p = 0;
     while (p + 1 < b.n && b.tile_start[p + 1] <= item) ++p;
-    corr_tile<PREC, NW, decltype(con), kArgmax>(b.piece[p], item - b.tile_start[p], sm, con);
+    corr_tile<PREC, NW, decltype(con), kArgmax, false>(b.piece[p], item - b.tile_start[p], sm, con);
     if (threadIdx.x == 0) *sm.item = next;
     __syncthreads();
     item = *sm.item;
