@@ -43,7 +43,7 @@ HBM_PEAK = 8000.0          # GB/s
 # FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) counters calibrated on a 1 GiB
 # copy (profiles/mra_c1_hbm_traffic.md).  Set to None when the kernel changes
 # until the counters are taken again.
-CORR_FP32_TRAFFIC_BYTES = 4.572e9
+CORR_FP32_TRAFFIC_BYTES = 4.571e9
 
 
 def log(msg):
