@@ -558,7 +558,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     // slot 256 - 16 n1.  SPLIT: one loop per direction (each wave runs one),
     // so that either keeps its 16 reads at constant offsets from one address
     // (in one loop the compiler merges the two read sets into 31 per-element
-    // addresses); the kernels whose registers are full keep one loop.
+    // addresses); the 4-wave kernels, whose registers are full, keep one loop.
     if constexpr (SPLIT) {
       {
         auto pass2 = [&](auto dir_c) {
@@ -821,7 +821,7 @@ __global__ __launch_bounds__(NW * 64) void k_corr_batch(CorrBatch b) {
     if (threadIdx.x == 0) next = atomicAdd(b.counter, 1) + (int)gridDim.x;
     int p = 0;
     while (p + 1 < b.n && b.tile_start[p + 1] <= item) ++p;
-    corr_tile<PREC, NW, decltype(con), kArgmax, false>(b.piece[p], item - b.tile_start[p], sm, con);
+    corr_tile<PREC, NW, decltype(con), kArgmax, NW == 8>(b.piece[p], item - b.tile_start[p], sm, con);
     if (threadIdx.x == 0) *sm.item = next;
     __syncthreads();
     item = *sm.item;
