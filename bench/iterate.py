@@ -8,7 +8,7 @@ prints one JSON line: passes, particles reassigned per pass, wall time per
 pass, and how well the final classes recover the planted ones (the share of
 particles whose final class holds a majority of their planted class).
 
-    python -m paper_2011_05755_amd.iterate --precision fp32
+    python -m bench.iterate --precision fp32
 """
 
 from __future__ import annotations
@@ -35,7 +35,7 @@ def main(argv=None) -> int:
     import numpy as np
     import torch
 
-    from . import mra, synth
+    from paper_2011_05755_amd import mra, synth
     dev = torch.device("cuda", 0)
     w = dict(synth.WORKLOADS["mra_c1"])
     N = max(w["K"], int(round(w["N"] * args.n_scale)))

@@ -9,7 +9,7 @@ form, one alignment pass plus the class-average update is timed (wall clock
 over --reps passes after a warm-up, references resident), with the
 correlation kernel's own time from HIP events.  One JSON line per (K, form).
 
-    python -m paper_2011_05755_amd.ksweep --refs 10,20,50,100,200 --forms fp32,bf16
+    python -m bench.ksweep --refs 10,20,50,100,200 --forms fp32,bf16
 """
 
 from __future__ import annotations
@@ -35,7 +35,7 @@ def main(argv=None) -> int:
 
     import torch
 
-    from . import mra, synth
+    from paper_2011_05755_amd import mra, synth
     dev = torch.device("cuda", 0)
     L, r_min, r_max, T = 90, 1, 36, 3
     Ks = [int(k) for k in args.refs.split(",") if k]

@@ -8,7 +8,7 @@ reference, kernel time from HIP events and wall time per pass, like the
 paper's RFA timing over shift ranges (Fig. 5b); then one RFA loop from the
 plain mean runs at T = 3.  One JSON line per measurement.
 
-    python -m paper_2011_05755_amd.rfa_bench --shifts 1,2,3,4,5
+    python -m bench.rfa_bench --shifts 1,2,3,4,5
 """
 
 from __future__ import annotations
@@ -34,7 +34,7 @@ def main(argv=None) -> int:
 
     import torch
 
-    from . import mra, synth
+    from paper_2011_05755_amd import mra, synth
     dev = torch.device("cuda", 0)
     L, r_min, r_max = 76, 1, 35
     Ts = [int(t) for t in args.shifts.split(",") if t]

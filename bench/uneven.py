@@ -12,7 +12,7 @@ rings 1..L/2-2), each against its own resident refset.  For each precision:
 
 Prints one JSON line per precision.
 
-    python -m paper_2011_05755_amd.uneven --precisions bf16,fp32
+    python -m bench.uneven --precisions bf16,fp32
 """
 
 from __future__ import annotations
@@ -42,7 +42,7 @@ def main(argv=None) -> int:
     import numpy as np
     import torch
 
-    from . import autotune, mra, synth
+    from paper_2011_05755_amd import autotune, mra, synth
     dev = torch.device("cuda", 0)
     specs = synth.uneven_stack_specs(args.stacks, seed=args.seed)
     t0 = time.perf_counter()

@@ -83,3 +83,33 @@ def test_wrong_average_rotation_sense_is_caught(monkeypatch):
 
     monkeypatch.setattr(oracle, "averages", negated)
     assert _fails(pins.test_averages_undo_quarter_turns_shifts_and_mirrors_exactly)
+
+
+def test_runner_up_that_keeps_the_winner_is_caught(monkeypatch):
+    """cc2 taken over the whole table (winner included) equals cc."""
+    orig = mra_oracle.align
+
+    def winner_kept(parts, refs, g, batch=8):
+        res = orig(parts, refs, g, batch)
+        res["cc2"] = res["cc"].copy()
+        return res
+
+    monkeypatch.setattr(oracle, "align", winner_kept)
+    assert _fails(pins.test_winner_and_runner_up_of_linear_images_closed_form, 1)
+    assert _fails(pins.test_winner_and_runner_up_of_linear_images_closed_form, 0)
+
+
+def test_runner_up_of_the_wrong_order_is_caught(monkeypatch):
+    """A cc2 read from the third-best candidate (or any other than the
+    second) is caught as well."""
+    orig = mra_oracle.align
+
+    def third(parts, refs, g, batch=8):
+        res = orig(parts, refs, g, batch)
+        tab = oracle.cc_table(parts, refs, g)
+        for i in range(len(res["cc2"])):
+            res["cc2"][i] = np.sort(tab[i].reshape(-1))[-3]
+        return res
+
+    monkeypatch.setattr(oracle, "align", third)
+    assert _fails(pins.test_winner_and_runner_up_of_linear_images_closed_form, 1)

@@ -88,6 +88,62 @@ def test_cc_of_linear_images_closed_form(m, normalize):
             np.testing.assert_allclose(tab[m, sy + 2, sx + 2], c, rtol=1e-12, atol=1e-9)
 
 
+
+def _linear_cc_closed_form(g, part, refs):
+    """Closed-form CC table [K, M, 2T+1 (sy), 2T+1 (sx), n_phi] of a linear
+    particle image against linear references (same formula as above), in
+    the order of the flat candidate index."""
+    dp, bp, gp = part
+    n = g.n_phi
+    T = g.shift_max
+    r = np.arange(g.r_min, g.r_max + 1, dtype=np.float64)
+    phi = 2 * np.pi * np.arange(n) / n
+    out = np.zeros((len(refs), g.n_mirror, 2 * T + 1, 2 * T + 1, n))
+    for k, (dq, bq, gq) in enumerate(refs):
+        nu = math.sqrt(np.sum(r * (n * dq * dq + 0.5 * n * r * r * (bq * bq + gq * gq))))
+        for m in range(g.n_mirror):
+            gprime = (1 - 2 * m) * gp
+            for sy in range(-T, T + 1):
+                for sx in range(-T, T + 1):
+                    D = dp + bp * sx + gp * sy
+                    c = np.zeros(n)
+                    for rr in r:
+                        c += rr * (n * D * dq + 0.5 * n * rr * rr * ((bp * bq + gprime * gq) * np.cos(phi)
+                                                                     + (bp * gq - gprime * bq) * np.sin(phi)))
+                    out[k, m, sy + T, sx + T] = c / nu if g.normalize else c
+    return out
+
+
+@pytest.mark.parametrize("mirror", [0, 1])
+def test_winner_and_runner_up_of_linear_images_closed_form(mirror):
+    """Algorithm 1's arg-max and the top-two gap: on linear images the whole
+    CC table is known in closed form, so the winner is its largest entry
+    (decoded to ref, shifts, mirror and psi = -a mod n_phi) and cc2 is its
+    second-largest entry, i.e. the best over every candidate but the
+    winner.  The case is chosen with a clear gap between the two, so a cc2
+    that kept the winner would read cc and fail."""
+    g = Geometry(L=64, r_min=2, r_max=18, n_phi=32, shift_max=2, mirror=mirror)
+    part = (0.4, 0.21, -0.37)
+    refs = [(-0.3, 0.45, 0.17), (0.25, -0.12, 0.41), (0.5, 0.3, 0.05)]
+    img = linear_image(g.L, *part)
+    ref_imgs = np.stack([linear_image(g.L, *q) for q in refs])
+    table = _linear_cc_closed_form(g, part, refs).reshape(-1)
+    order = np.argsort(-table, kind="stable")
+    top1, top2 = table[order[0]], table[order[1]]
+    assert top1 - top2 > 1e-6 * abs(top1)           # a real gap: the pin has teeth
+    res = oracle.align(img[None], ref_imgs, g)
+    assert res["flat_index"][0] == order[0]
+    assert res["cc"][0] == pytest.approx(top1, rel=1e-11)
+    assert res["cc2"][0] == pytest.approx(top2, rel=1e-11)
+    S1, n = 2 * g.shift_max + 1, g.n_phi
+    a = order[0] % n
+    sx = (order[0] // n) % S1 - g.shift_max
+    sy = (order[0] // (n * S1)) % S1 - g.shift_max
+    m = (order[0] // (n * S1 * S1)) % g.n_mirror
+    k = order[0] // (n * S1 * S1 * g.n_mirror)
+    assert (res["ref"][0], res["mirror"][0], res["shift_x"][0], res["shift_y"][0]) == (k, m, sx, sy)
+    assert res["psi"][0] == (n - a) % n
+
 @pytest.mark.parametrize("normalize", [0, 1])
 def test_self_cc_is_the_weighted_ring_norm(normalize):
     rng = np.random.default_rng(5)
