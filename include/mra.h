@@ -140,6 +140,16 @@ int mra_destroy(mra_ctx* ctx);
 int mra_load_refs(mra_ctx* ctx, int32_t refset_id, const float* refs, int32_t K,
                   const mra_geom* g);
 
+/* Validate a geometry for K references searched over shifts {-T..T}^2
+ * (T = shift_max, or g->shift_max when shift_max < 0) without a context or
+ * a device: returns MRA_OK when mra_load_refs and mra_align would accept
+ * it, else MRA_E_INVAL.  Besides the ranges above, the flat candidate index
+ * is an int32, so K * M * (2T+1)^2 * n_phi must be below 2^31 (M = 2 with
+ * mirror search: with mirrors at most 85 598 references at T = 3 and
+ * 14 513 at T = 8; use several refsets beyond that), and
+ * the box plus search range must fit the resampler's LDS staging. */
+int mra_check_geom(const mra_geom* g, int32_t K, int32_t shift_max);
+
 /* Free one refset.  MRA_E_NOREF if absent. */
 int mra_unload_refs(mra_ctx* ctx, int32_t refset_id);
 

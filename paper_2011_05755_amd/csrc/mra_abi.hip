@@ -170,6 +170,31 @@ void check_geom(const mra_geom* g) {
   if (g->rescore_rows < 0 || g->rescore_rows > 8) bad("rescore_rows must be in [0, 8]");
 }
 
+// Range of the floor offsets of the polar stencil (r cos, r sin) over the
+// rings of g: the pixels a zero shift touches lie in [c + dmin, c + dmax + 1].
+void stencil_range(const mra_geom& g, int& dmin, int& dmax) {
+  std::vector<double> cs, sn;
+  build_cs(kNphi, cs, sn);
+  dmin = 0;
+  dmax = 0;
+  for (int r = g.r_min; r <= g.r_max; ++r)
+    for (int j = 0; j < kNphi; ++j) {
+      const int fx = (int)std::floor(r * cs[j]), fy = (int)std::floor(r * sn[j]);
+      dmin = std::min({dmin, fx, fy});
+      dmax = std::max({dmax, fx, fy});
+    }
+}
+
+// The flat candidate index iota = (((k M + m) S1 + sy) S1 + sx) n_phi + a is
+// an int32 in every kernel and 0x7fffffff marks "no candidate", so
+// K * M * S * n_phi must stay below 2^31.
+void check_index_range(int64_t K, int M, int T) {
+  const int64_t S1 = 2 * (int64_t)T + 1;
+  if (K * M * S1 * S1 * kNphi > (int64_t)INT32_MAX)
+    throw Fail{MRA_E_INVAL, "K * mirrors * (2 shift_max + 1)^2 * n_phi must be below 2^31 (int32 candidate index); "
+                            "split the references into several refsets"};
+}
+
 Refset& get_refset(mra_ctx* c, int32_t id) {
   auto it = c->refs.find(id);
   if (it == c->refs.end()) throw Fail{MRA_E_NOREF, "refset " + std::to_string(id) + " is not loaded"};
@@ -183,6 +208,7 @@ struct Plan {
 
 Plan plan_for(const Refset& rs, int T) {
   if (T < 0 || T > 8) throw Fail{MRA_E_INVAL, "shift_max must be in [0, 8]"};
+  check_index_range(rs.K, rs.g.mirror ? 2 : 1, T);
   Plan p;
   p.T = T;
   p.S1 = 2 * T + 1;
@@ -538,6 +564,7 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
 void load_refs_impl(mra_ctx* c, int32_t id, const float* refs, int32_t K, const mra_geom* g) {
   check_geom(g);
   if (K < 1) throw Fail{MRA_E_INVAL, "K must be >= 1"};
+  check_index_range(K, g->mirror ? 2 : 1, g->shift_max);
   if (!refs) throw Fail{MRA_E_INVAL, "refs is NULL"};
   Refset rs;
   rs.g = *g;
@@ -802,6 +829,26 @@ int mra_destroy(mra_ctx* c) {
 
 int mra_load_refs(mra_ctx* c, int32_t id, const float* refs, int32_t K, const mra_geom* g) {
   return guard(c, [&] { load_refs_impl(c, id, refs, K, g); });
+}
+
+int mra_check_geom(const mra_geom* g, int32_t K, int32_t shift_max) {
+  try {
+    check_geom(g);
+    if (K < 1) return MRA_E_INVAL;
+    const int T = shift_max < 0 ? g->shift_max : shift_max;
+    if (T > 8) return MRA_E_INVAL;
+    check_index_range(K, g->mirror ? 2 : 1, T);
+    Refset rs;
+    rs.g = *g;
+    rs.K = K;
+    stencil_range(*g, rs.dmin, rs.dmax);
+    (void)plan_for(rs, T);
+    return MRA_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  } catch (...) {
+    return MRA_E_INVAL;
+  }
 }
 
 int mra_unload_refs(mra_ctx* c, int32_t id) {

@@ -24,7 +24,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 DEFAULT_RESCORE_ROWS = 4
 
 EXPORTS = (
-    "mra_create", "mra_destroy", "mra_load_refs", "mra_unload_refs", "mra_refset_info",
+    "mra_create", "mra_destroy", "mra_load_refs", "mra_check_geom", "mra_unload_refs", "mra_refset_info",
     "mra_align", "mra_update_averages", "mra_classify", "mra_rfa", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
     "mra_debug_polar",
     "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_profile", "mra_profile_read",
@@ -74,6 +74,7 @@ def load_library() -> ctypes.CDLL:
         "mra_create": [ctypes.POINTER(vp), ctypes.c_int, vp, u64],
         "mra_destroy": [vp],
         "mra_load_refs": [vp, i32, vp, i32, ctypes.POINTER(Geom)],
+        "mra_check_geom": [ctypes.POINTER(Geom), i32, i32],
         "mra_unload_refs": [vp, i32],
         "mra_refset_info": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(Geom)],
         "mra_align": [vp, i32, vp, i64, ctypes.POINTER(Result)],
@@ -164,6 +165,40 @@ class Refset:
         return self.r_max - self.r_min + 1
 
 
+_RESULT_DTYPES = dict(ref=torch.int32, shift_x=torch.int32, shift_y=torch.int32, psi=torch.int32,
+                      mirror=torch.int32, cc=torch.float32, cc2=torch.float32, flat_index=torch.int32,
+                      psi_frac=torch.float32)
+_REQUIRED = ("ref", "shift_x", "shift_y", "psi", "mirror", "cc")
+
+
+def _check_result(out: "AlignResult", N: int, device: torch.device, name: str = "out",
+                  required=_REQUIRED):
+    """Every array the library will write (or read) must be a contiguous 1-D
+    tensor of the field's dtype with at least N elements on `device`: the C
+    ABI takes raw pointers and cannot check lengths itself."""
+    for field, dtype in _RESULT_DTYPES.items():
+        t = getattr(out, field)
+        if t is None:
+            if field in required:
+                raise ValueError(f"{name}.{field} is required")
+            continue
+        if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.dim() != 1 or t.shape[0] < N \
+                or not t.is_contiguous() or t.device != device:
+            raise ValueError(f"{name}.{field} must be a contiguous 1-D {dtype} tensor of length >= {N} "
+                             f"on {device}")
+
+
+def check_geom(L: int, r_min: int, r_max: int, shift_max: int, K: int, n_phi: int = 256, mirror: bool = True,
+               precision: str = "fp32", normalize: bool = True, rescore_rows: int = 0,
+               search_shift: int = -1) -> int:
+    """mra_check_geom: MRA_OK when the library accepts the geometry for K
+    references (searched at search_shift, or shift_max when negative),
+    else the error code.  Needs no device."""
+    lib = load_library()
+    g = Geom(L, r_min, r_max, n_phi, shift_max, int(mirror), PRECISIONS[precision], int(normalize), rescore_rows)
+    return lib.mra_check_geom(ctypes.byref(g), K, search_shift)
+
+
 def _check_images(x: torch.Tensor, L: int, name: str):
     if not (x.is_cuda and x.dtype == torch.float32 and x.dim() == 3 and x.shape[1] == L
             and x.shape[2] == L and x.is_contiguous()):
@@ -238,6 +273,7 @@ class Context:
         N = parts.shape[0]
         if out is None:
             out = AlignResult.empty(N, parts.device, with_cc2=with_cc2, with_psi_frac=with_psi_frac)
+        _check_result(out, N, parts.device)
         res = out.c_struct()
         self._check(self.lib.mra_align(self._h, refset_id, _ptr(parts), N, ctypes.byref(res)))
         return out
@@ -247,6 +283,7 @@ class Context:
         arr = (Stack * len(stacks))()
         for i, (rid, parts, T, out) in enumerate(stacks):
             _check_images(parts, self.refsets[rid].L, "parts")
+            _check_result(out, parts.shape[0], parts.device, name=f"stacks[{i}].out")
             arr[i] = Stack(rid, parts.data_ptr(), parts.shape[0], T, out.c_struct())
         self._check(self.lib.mra_align_batch(self._h, arr, len(stacks)))
 
@@ -258,6 +295,7 @@ class Context:
         _check_images(averages, rs.L, "averages")
         if averages.shape[0] != rs.K:
             raise ValueError("averages must have K images")
+        _check_result(params, parts.shape[0], parts.device, name="params", required=_REQUIRED[:5])
         counts = torch.empty(rs.K, dtype=torch.int32, device=parts.device)
         p = params.c_struct()
         self._check(self.lib.mra_update_averages(self._h, refset_id, _ptr(parts), parts.shape[0],
@@ -277,6 +315,7 @@ class Context:
         N, K = parts.shape[0], averages.shape[0]
         if out is None:
             out = AlignResult.empty(N, parts.device, with_cc2=with_cc2)
+        _check_result(out, N, parts.device)
         counts = torch.empty(K, dtype=torch.int32, device=parts.device)
         if rescore_rows is None:
             rescore_rows = DEFAULT_RESCORE_ROWS if precision != "fp32" else 0
@@ -310,6 +349,7 @@ class Context:
             raise ValueError(f"average must be a contiguous float32 CUDA tensor [{L}, {L}]")
         if out is None:
             out = AlignResult.empty(N, parts.device, with_cc2=with_cc2)
+        _check_result(out, N, parts.device)
         g = Geom(L, r_min, r_max, n_phi, shift_max, int(mirror), 0, int(normalize))
         res = out.c_struct()
         n_iter = ctypes.c_int32()

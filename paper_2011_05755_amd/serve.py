@@ -17,6 +17,11 @@ copy on the device); their device images are freed when their last piece
 completes.  Pieces never change results: every request's output equals
 ``mra_align`` on it alone, bit for bit.
 
+A request that the executor refuses (its admission or a step with its
+pieces raises, e.g. a refset that is not loaded or images of the wrong box)
+completes with ``error`` set and its budget released; the other requests
+of that step are launched again without it and go on unchanged.
+
 The GPU side sits behind a small executor interface (``admit(req)``,
 ``launch(pieces) -> handle``, ``done(handle)``, ``wait(handle)``,
 ``release(req)``) so that the scheduler runs unchanged against a stand-in on
@@ -54,6 +59,7 @@ class Request:
     next: int = 0             # first particle not yet scheduled
     inflight: int = 0         # pieces launched and not yet completed
     finished: int = 0         # particles completed
+    error: str | None = None  # set when the request failed (its results are not valid)
 
     @property
     def S(self) -> int:
@@ -89,6 +95,7 @@ class Server:
         self.active: list[Request] = []      # admitted, not finished (admission order)
         self.inflight: list[tuple[object, list[Piece]]] = []
         self.finished: list[Request] = []
+        self.failed: list[Request] = []
         self.used = 0
         self.peak_used = 0
         self._next_id = 0
@@ -111,8 +118,45 @@ class Server:
             r.t_admit = now
             self.used += r.footprint()
             self.peak_used = max(self.peak_used, self.used)
-            self.ex.admit(r)
             self.active.append(r)
+            try:
+                self.ex.admit(r)
+            except Exception as e:          # noqa: BLE001 - any refusal fails this request only
+                self._fail(r, e, now)
+
+    def _fail(self, r: Request, err: Exception, now: float):
+        """End request r with an error: free its budget and device images;
+        pieces of it still in flight are ignored when they complete."""
+        if r.error is not None:
+            return
+        r.error = f"{type(err).__name__}: {err}"
+        r.t_done = now
+        if r in self.active:
+            self.active.remove(r)
+        self.used -= r.footprint()
+        try:
+            self.ex.release(r)
+        finally:
+            self.failed.append(r)
+
+    def _launch(self, pieces: list[Piece], now: float):
+        """Launch one step; if the executor refuses it, launch each request's
+        pieces on their own so that only the offending requests fail."""
+        try:
+            self.inflight.append((self.ex.launch(pieces), pieces))
+            return
+        except Exception as e:              # noqa: BLE001
+            by_req: dict[int, list[Piece]] = {}
+            for p in pieces:
+                by_req.setdefault(p.req.rid, []).append(p)
+            if len(by_req) == 1:
+                self._fail(pieces[0].req, e, now)
+                return
+        for ps in by_req.values():
+            try:
+                self.inflight.append((self.ex.launch(ps), ps))
+            except Exception as e:          # noqa: BLE001
+                self._fail(ps[0].req, e, now)
 
     # ---- steps ----
     def _plan_step(self) -> list[Piece]:
@@ -140,6 +184,8 @@ class Server:
         for h, pieces in self.inflight:
             if self.ex.done(h):
                 for p in pieces:
+                    if p.req.error is not None:
+                        continue
                     p.req.inflight -= 1
                     p.req.finished += p.n
                     if p.req.finished == p.req.N:
@@ -160,7 +206,7 @@ class Server:
             pieces = self._plan_step()
             if not pieces:
                 break
-            self.inflight.append((self.ex.launch(pieces), pieces))
+            self._launch(pieces, now)
             self.steps += 1
         return bool(self.waiting or self.active or self.inflight)
 
@@ -209,7 +255,7 @@ def run_trace(server: Server, arrivals: list[tuple[float, Request]], clock=time.
     first = min((r.t_arrival for r in measured), default=0.0)
     t_last = max((r.t_done for r in measured), default=t_end)
     return dict(requests=len(measured), warmup_requests=len(server.finished) - len(measured),
-                particles=parts, steps=server.steps,
+                failed_requests=len(server.failed), particles=parts, steps=server.steps,
                 p50_s=percentile(lat, 50), p99_s=percentile(lat, 99), max_s=max(lat) if lat else math.nan,
                 mean_s=sum(lat) / len(lat) if lat else math.nan,
                 makespan_s=t_last - first, particles_per_s=parts / max(t_last - first, 1e-9),
@@ -280,7 +326,7 @@ def make_refsets(ctx, n_sets: int, seed: int, precision: str, specs=None):
         refs = synth.render_refs(blobs).to(dev)
         ctx.load_refs(i, refs, r_min=sp["r_min"], r_max=sp["r_max"], shift_max=sp["shift_max"],
                       precision=precision)
-        sets.append(dict(id=i, blobs=blobs, **sp))
+        sets.append(dict(id=i, blobs=blobs, refs=refs, **sp))
     return sets
 
 
