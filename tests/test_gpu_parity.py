@@ -14,6 +14,7 @@ import torch
 
 import oracle
 from paper_2011_05755_amd import synth
+from parity import agreement, check_align, check_pose, pose_gap
 
 pytestmark = pytest.mark.gpu
 
@@ -43,17 +44,6 @@ def make_case(L, K, T, N, snr, seed, rho=None, r_max=None, mirror=True, n_phi_gr
 def geom(L, r_max, T, mirror=True, normalize=True, r_min=1):
     return oracle.Geometry(L=L, r_min=r_min, r_max=r_max, n_phi=256, shift_max=T, mirror=int(mirror),
                            normalize=int(normalize))
-
-
-def check_align(got, want, tol, cc_tol=None):
-    cc_tol = tol if cc_tol is None else cc_tol
-    rel = np.abs(got["cc"] - want["cc"]) / np.abs(want["cc"])
-    assert rel.max() <= cc_tol, f"max rel CC err {rel.max():.3g}"
-    ok_gap = (want["cc"] - want["cc2"]) >= tol * np.abs(want["cc"])
-    for key in ("ref", "shift_x", "shift_y", "mirror", "psi"):
-        bad = np.nonzero((got[key] != want[key]) & ok_gap)[0]
-        assert bad.size == 0, f"{key} differs at {bad[:10]}: got {got[key][bad[:5]]} want {want[key][bad[:5]]}"
-    return rel.max(), ok_gap.mean()
 
 
 def test_reference_preparation(ctx):
@@ -185,22 +175,29 @@ def test_align_mixed_precision_with_fp32_rescore(ctx, precision):
     ctx.load_refs(6, refs, r_min=1, r_max=30, shift_max=T, precision=precision)
     res = ctx.align(6, parts).to_numpy()
     g = geom(L, 30, T)
-    want = oracle.align(parts.cpu().numpy(), refs.cpu().numpy(), g)
+    pn, rn = parts.cpu().numpy(), refs.cpu().numpy()
+    want = oracle.align(pn, rn, g)
     # CC within 2e-3 of the oracle's best; parameters equal wherever the
     # oracle's top-two gap is at least 2e-3
     err, frac = check_align(res, want, 2e-3)
+    # the teeth: the pose (reference, shifts, mirror) equal and psi within one
+    # step wherever every other pose is 2e-3 below the winner in the oracle
+    gap = pose_gap(oracle.cc_table(pn, rn, g))
+    n_pose = check_pose(res, want, gap, 2e-3, min_decided=N // 4)
     # the reported CC is the FP32 re-score of the chosen candidate: equal to
     # the oracle's value of that same candidate to FP32 accuracy
-    qhat, _ = oracle.reference_polar(refs.cpu().numpy(), g)
-    pn = parts.cpu().numpy()
-    agree = 0
+    qhat, _ = oracle.reference_polar(rn, g)
     for n in range(N):
         a = (256 - res["psi"][n]) % 256
         v = oracle.candidate_cc(pn[n], qhat[res["ref"][n]], g, res["shift_x"][n], res["shift_y"][n],
                                 res["mirror"][n], a)
         assert abs(res["cc"][n] - v) <= 1e-5 * abs(v), (n, res["cc"][n], v)
-        agree += all(res[k][n] == want[k][n] for k in ("ref", "shift_x", "shift_y", "mirror", "psi"))
-    log(f"  max rel CC err {err:.2e}; argmax agreement {agree}/{N}; decided fraction {frac:.3f}")
+    agree = int(agreement(res, want).sum())
+    log(f"  max rel CC err {err:.2e}; argmax agreement {agree}/{N}; decided by the top-two gap {frac:.3f}, "
+        f"by pose {n_pose}/{N}")
+    # with the default FP32 re-ranking of the 4 best rows the 16-bit forms
+    # pick the oracle's exact winner for nearly every particle
+    assert agree >= 0.9 * N, f"argmax agreement {agree}/{N}"
 
 
 def test_align_mirror_off_normalize_off_no_shift(ctx):

@@ -129,3 +129,42 @@ def test_steps_stay_within_the_row_budget_and_share_it():
         assert rows <= 10_000 + max(S.values())
     first = ex.log[0][1]
     assert [rid for rid, _, _ in first] == [r.rid for r in rs]     # every active request in the first step
+
+
+class RefusingExecutor(FakeExecutor):
+    """Refuses requests on refset 99 at launch and on refset 98 at admission
+    (as the library refuses a refset that is not loaded)."""
+
+    def admit(self, r):
+        if r.refset_id == 98:
+            raise RuntimeError("refset 98 is not loaded")
+        super().admit(r)
+
+    def launch(self, pieces):
+        if any(p.req.refset_id == 99 for p in pieces):
+            raise RuntimeError("refset 99 is not loaded")
+        return super().launch(pieces)
+
+
+def test_a_failing_request_fails_alone_and_the_others_complete():
+    clk = SimClock()
+    ex = RefusingExecutor(clk)
+    srv = serve.Server(ex, hbm_budget=1 << 40, step_rows=4000)
+    good = [req(500), req(120, T=1), req(700, T=3)]
+    bad_launch, bad_admit = req(300, rid_hint=99), req(50, rid_hint=98)
+    arrivals = [(0.0, good[0]), (0.0, bad_launch), (0.001, good[1]), (0.002, bad_admit), (0.003, good[2])]
+    stats = serve.run_trace(srv, arrivals, clock=clk, sleep=clk.sleep)
+    assert stats["requests"] == 3 and stats["failed_requests"] == 2
+    assert stats["particles"] == sum(r.N for r in good)
+    for r in good:                                   # every good particle scheduled exactly once
+        assert r.error is None and r.t_done is not None
+        spans = sorted((n0, n) for _, ps in ex.log for rid, n0, n in ps if rid == r.rid)
+        assert sum(n for _, n in spans) == r.N and spans[0][0] == 0
+    assert "refset 99" in bad_launch.error and "refset 98" in bad_admit.error
+    assert bad_launch.t_done is not None and bad_admit.t_done is not None
+    assert not any(rid == bad_launch.rid for _, ps in ex.log for rid, _, _ in ps)
+    assert bad_launch in srv.failed and bad_admit in srv.failed and bad_launch not in srv.finished
+    assert srv.used == 0 and not srv.active               # budgets released
+    assert sorted(ex.released) == sorted(r.rid for r in good + [bad_launch, bad_admit])
+    # a step that held the bad request's piece was launched again without it
+    assert any(len(ps) >= 2 for _, ps in ex.log)
