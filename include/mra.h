@@ -167,6 +167,25 @@ int mra_refset_info(mra_ctx* ctx, int32_t refset_id, int32_t* K, mra_geom* g);
 int mra_align(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
               mra_result* out);
 
+/* mra_align for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results as mra_align, bit for bit, but
+ * the per-chunk buffers (particle operand, row results, FP16 scales, the
+ * runner-up's winner copy) live in a fixed 256 MiB device array that every
+ * device the library runs on holds from mra_create until the process ends,
+ * instead of the context's workspace.  Nothing is allocated or freed and no
+ * memset node is recorded: padding is cleared by a kernel.  The refset must
+ * already be loaded (mra_load_refs allocates).  Large N is processed in
+ * chunks that fit the array (about 140 particles per chunk at L = 76, 49
+ * shifts, 35 rings), so throughput is lower than mra_align's with its
+ * multi-GiB workspace.  All calls on one device share its array: calls that
+ * overlap in time on one device (several streams, contexts or threads) race
+ * and give undefined results; serialise them.  Errors: as mra_align, and
+ * MRA_E_INVAL if one particle's buffers exceed the array (not reachable
+ * within the geometry limits above). */
+int mra_align_noalloc(mra_ctx* ctx, int32_t refset_id, const float* parts, int64_t N,
+                      mra_result* out);
+
 /* Class-average update (Algorithm 1: apply the alignment parameters to each
  * image, compute new Y' from the aligned images).  For each class k with
  * n_k > 0:  Y'_k(u) = (1/n_k) sum_{ref_n = k} Bil(X_n; c + s_n + Mir^{m_n} Rot(psi_n 2pi/n_phi)(u - c)),

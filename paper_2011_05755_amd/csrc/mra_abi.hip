@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,19 @@ using namespace mra;
 namespace {
 
 constexpr size_t kLdsMax = 160 * 1024;
+
+// Device scratch of mra_align_noalloc (callers that cannot allocate): the
+// per-chunk particle operand and row results live here instead of the
+// context's workspace.  Each device holds its own copy for the life of the
+// process; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the device (scratch_ptr), never through
+// the symbol itself.
+constexpr size_t kScratchBytes = 256ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 struct DevBuf {
   void* p = nullptr;
@@ -59,6 +73,7 @@ struct mra_ctx {
   std::map<std::string, DevBuf> ws;
   int n_cu = 256;
   int* counter = nullptr;  // work-item counter of persistent launches
+  void* scratch = nullptr; // this device's copy of the no-allocation scratch
   bool profiling = false;
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
 };
@@ -70,6 +85,21 @@ void hip_check(mra_ctx* c, hipError_t e, const char* what) {
     c->failed = true;
     throw Fail{MRA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
   }
+}
+
+// Address of the no-allocation scratch on c's device (current at the call):
+// resolved once per device, kept for every later context on it.
+void* scratch_ptr(mra_ctx* c) {
+  if (c->device < 0 || c->device >= kMaxDevices) throw Fail{MRA_E_INVAL, "device ordinal out of range"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  void*& p = g_scratch_ptr[c->device];
+  if (!p) {
+    void* q = nullptr;
+    hip_check(c, hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!q) throw Fail{MRA_E_DEVICE, "no device address for the scratch array"};
+    p = q;
+  }
+  return p;
 }
 
 void* alloc(mra_ctx* c, size_t bytes, const char* what) {
@@ -244,6 +274,70 @@ int64_t chunk_particles(mra_ctx* c, const Refset& rs, const Plan& p) {
   return std::max<int64_t>(n, 1);
 }
 
+// Device buffers of one alignment chunk of nc particles.
+struct ChunkBufs {
+  float* A = nullptr;       // particle operand, ceil(nc S / 8) row tiles
+  float* rcc = nullptr;     // [nc S] best CC per row
+  int* ridx = nullptr;      // [nc S] its flat index
+  float* maxabs = nullptr;  // FP16: [nc] max |pixel|
+  int32_t* win = nullptr;   // cc2: [nc] chunk-local winner copy
+};
+
+size_t tile_bytes_of(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * sizeof(float); }
+
+// Lays the buffers of an nc-particle chunk out from `base` (256-byte
+// aligned pieces); returns the bytes used.  base = nullptr only measures.
+size_t carve_chunk(const Refset& rs, const Plan& p, int64_t nc, bool fp16, bool cc2, char* base, ChunkBufs* b) {
+  const size_t rows = (size_t)nc * p.S;
+  const size_t tiles = (rows + kRowTile - 1) / kRowTile;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  char* A = take(tiles * tile_bytes_of(rs));
+  char* rcc = take(rows * sizeof(float));
+  char* ridx = take(rows * sizeof(int));
+  char* mx = fp16 ? take((size_t)nc * sizeof(float)) : nullptr;
+  char* win = cc2 ? take((size_t)nc * sizeof(int32_t)) : nullptr;
+  if (b) {
+    b->A = (float*)A;
+    b->rcc = (float*)rcc;
+    b->ridx = (int*)ridx;
+    b->maxabs = (float*)mx;
+    b->win = (int32_t*)win;
+  }
+  return off;
+}
+
+// Buffers of a chunk from the context's workspace (grown on demand).
+ChunkBufs ws_chunk(mra_ctx* c, const Refset& rs, const Plan& p, int nc, const mra_result* out) {
+  ChunkBufs b;
+  const size_t rows = (size_t)nc * p.S;
+  const size_t tiles = (rows + kRowTile - 1) / kRowTile;
+  b.A = (float*)ws_get(c, "A", tiles * tile_bytes_of(rs));
+  b.rcc = (float*)ws_get(c, "row_cc", rows * sizeof(float));
+  b.ridx = (int*)ws_get(c, "row_idx", rows * sizeof(int));
+  if (rs.g.precision == kFP16) b.maxabs = (float*)ws_get(c, "maxabs", (size_t)nc * sizeof(float));
+  if (out && out->cc2) b.win = (int32_t*)ws_get(c, "win", (size_t)nc * sizeof(int32_t));
+  return b;
+}
+
+// Largest chunk whose buffers fit `bytes` of scratch (0 if not one particle).
+int64_t scratch_chunk(const Refset& rs, const Plan& p, bool cc2, size_t bytes) {
+  const bool fp16 = rs.g.precision == kFP16;
+  if (carve_chunk(rs, p, 1, fp16, cc2, nullptr, nullptr) > bytes) return 0;
+  // the buffers grow with the chunk: bisect for the largest that fits
+  int64_t lo = 1, hi = std::min<int64_t>(INT32_MAX / p.S / 2, (int64_t)(bytes / ((size_t)p.S * 8)) + 1);
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (carve_chunk(rs, p, mid, fp16, cc2, nullptr, nullptr) <= bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Sub-step angles of particles n0 .. n0 + nc - 1 from their final parameters.
 void refine_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, int64_t n0, int64_t nc,
                   const mra_result* out) {
@@ -269,21 +363,23 @@ void refine_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* part
 // (-> FP32 re-score for 16-bit contractions).  mode 0 = production,
 // mode 3 = debug CC table into `table`.
 void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, int64_t n0, int nc,
-               const mra_result* out, float* table) {
+               const mra_result* out, float* table, const ChunkBufs& bufs) {
   hipStream_t st = c->stream;
   const int L = rs.g.L;
   const int rows = nc * p.S;
   const int tiles = (rows + kRowTile - 1) / kRowTile;
-  const size_t tile_bytes = (size_t)kSlots * rs.R4 * 64 * sizeof(float);
-  float* A = (float*)ws_get(c, "A", (size_t)tiles * tile_bytes);
-  float* rcc = (float*)ws_get(c, "row_cc", (size_t)rows * sizeof(float));
-  int* ridx = (int*)ws_get(c, "row_idx", (size_t)rows * sizeof(int));
-  if (rows % kRowTile) hip_check(c, hipMemsetAsync(A + (size_t)(tiles - 1) * tile_bytes / sizeof(float), 0, tile_bytes, st), "memset");
+  const size_t tile_bytes = tile_bytes_of(rs);
+  float* A = bufs.A;
+  float* rcc = bufs.rcc;
+  int* ridx = bufs.ridx;
+  // rows past the chunk in its last tile are read as zeros
+  if (rows % kRowTile)
+    hip_check(c, launch_fill_zero(A + (size_t)(tiles - 1) * tile_bytes / sizeof(float), tile_bytes, st), "fill");
   const float* src = parts + (size_t)n0 * L * L;
 
   float* maxabs = nullptr;
   if (rs.g.precision == kFP16) {
-    maxabs = (float*)ws_get(c, "maxabs", (size_t)nc * sizeof(float));
+    maxabs = bufs.maxabs;
     timed(c, "maxabs", [&] { hip_check(c, launch_part_maxabs(src, nc, L, maxabs, st), "maxabs"); });
   }
 
@@ -324,7 +420,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ma.ref = out->ref; ma.shift_x = out->shift_x; ma.shift_y = out->shift_y;
   ma.psi = out->psi; ma.mirror = out->mirror; ma.flat = out->flat_index;
   ma.cc = out->cc; ma.cc2 = out->cc2;
-  int32_t* win = out->cc2 ? (int32_t*)ws_get(c, "win", (size_t)nc * sizeof(int32_t)) : nullptr;
+  int32_t* win = out->cc2 ? bufs.win : nullptr;
   ma.win = win;
   timed(c, "merge", [&] { hip_check(c, launch_merge(ma, st), "merge"); });
 
@@ -385,8 +481,10 @@ void run_single(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts,
   if (out->psi_frac) refine_chunk(c, rs, p, parts, 0, N, out);
 }
 
+// noalloc: the chunk buffers come from the device scratch array instead of
+// the workspace, so nothing is allocated (the path of mra_align_noalloc).
 void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, const mra_result* out,
-                float* table) {
+                float* table, bool noalloc = false) {
   Refset& rs = get_refset(c, id);
   if (N < 0) throw Fail{MRA_E_INVAL, "N must be >= 0"};
   if (N == 0) return;
@@ -397,11 +495,21 @@ void align_impl(mra_ctx* c, int32_t id, const float* parts, int64_t N, int T, co
     run_single(c, rs, p, parts, N, out);
     return;
   }
-  const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
+  int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
+  if (noalloc) {
+    step = scratch_chunk(rs, p, out && out->cc2, kScratchBytes);
+    if (step < 1)
+      throw Fail{MRA_E_INVAL, "one particle's operand exceeds the " + std::to_string(kScratchBytes >> 20) +
+                                  " MiB no-allocation scratch"};
+    if (!c->scratch) throw Fail{MRA_E_DEVICE, "no-allocation scratch not resolved on this device"};
+  }
   for (int64_t n0 = 0; n0 < N; n0 += step) {
     const int nc = (int)std::min<int64_t>(step, N - n0);
     float* tab = table ? table + (size_t)n0 * rs.K * p.M * p.S * kNphi : nullptr;
-    run_chunk(c, rs, p, parts, n0, nc, out, tab);
+    ChunkBufs b;
+    if (noalloc) carve_chunk(rs, p, nc, rs.g.precision == kFP16, out && out->cc2, (char*)c->scratch, &b);
+    else b = ws_chunk(c, rs, p, nc, out);
+    run_chunk(c, rs, p, parts, n0, nc, out, tab, b);
   }
 }
 
@@ -421,7 +529,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
   if (w.size() == 1) {  // one piece fills the chip by itself: the plain per-chunk launches
     const Piece& pc = w[0];
     const mra_stack& sk = stacks[pc.stack];
-    run_chunk(c, *pc.rs, pc.p, sk.parts, pc.n0, pc.nc, &sk.out, nullptr);
+    run_chunk(c, *pc.rs, pc.p, sk.parts, pc.n0, pc.nc, &sk.out, nullptr, ws_chunk(c, *pc.rs, pc.p, pc.nc, &sk.out));
     return;
   }
   const Refset& rs0 = *w[0].rs;
@@ -458,7 +566,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     float* Ap = A + pc.a_off;
     const float* src = sk.parts + (size_t)pc.n0 * L * L;
     if (prow % kRowTile)
-      hip_check(c, hipMemsetAsync(Ap + (size_t)(ptiles - 1) * tile_floats, 0, tile_floats * sizeof(float), st), "memset");
+      hip_check(c, launch_fill_zero(Ap + (size_t)(ptiles - 1) * tile_floats, tile_floats * sizeof(float), st), "fill");
     float* mx = nullptr;
     if (maxabs) {
       mx = maxabs + part;
@@ -537,8 +645,10 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
     }
     if (s.out.cc2 || s.out.psi_frac) {  // runner-up or refinement: the per-chunk path
       const int64_t step = std::min<int64_t>(chunk_particles(c, rs, p), (int64_t)(INT32_MAX / p.S / 2));
-      for (int64_t n0 = 0; n0 < s.N; n0 += step)
-        run_chunk(c, rs, p, s.parts, n0, (int)std::min<int64_t>(step, s.N - n0), &s.out, nullptr);
+      for (int64_t n0 = 0; n0 < s.N; n0 += step) {
+        const int nc = (int)std::min<int64_t>(step, s.N - n0);
+        run_chunk(c, rs, p, s.parts, n0, nc, &s.out, nullptr, ws_chunk(c, rs, p, nc, &s.out));
+      }
       continue;
     }
     const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
@@ -798,6 +908,7 @@ int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_c
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
       c->n_cu = ncu;
+    c->scratch = scratch_ptr(c);
     c->counter = (int*)alloc(c, 256, "counter");
     c->cs64 = (double2*)alloc(c, kNphi * sizeof(double2), "cs64");
     c->cs32 = (float2*)alloc(c, kNphi * sizeof(float2), "cs32");
@@ -870,6 +981,10 @@ int mra_refset_info(mra_ctx* c, int32_t id, int32_t* K, mra_geom* g) {
 
 int mra_align(mra_ctx* c, int32_t id, const float* parts, int64_t N, mra_result* out) {
   return guard(c, [&] { align_impl(c, id, parts, N, -1, out, nullptr); });
+}
+
+int mra_align_noalloc(mra_ctx* c, int32_t id, const float* parts, int64_t N, mra_result* out) {
+  return guard(c, [&] { align_impl(c, id, parts, N, -1, out, nullptr, true); });
 }
 
 int mra_align_batch(mra_ctx* c, const mra_stack* stacks, int32_t n) {

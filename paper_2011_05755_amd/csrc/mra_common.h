@@ -173,6 +173,8 @@ hipError_t launch_rescore_batch(const RescoreBatch& b, hipStream_t st);
 hipError_t launch_refine(const RescoreArgs& a, hipStream_t st);  // psi_frac from the final parameters
 hipError_t launch_part_maxabs(const float* x, int n_part, int L, float* out, hipStream_t st);
 hipError_t launch_rfa(const RfaArgs& a, hipStream_t st);
+// zero `bytes` (a multiple of 16) at p (16-byte aligned) with a kernel
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 // count[0] += #{i : cls[i] != prev[i]}; then prev = cls
 hipError_t launch_count_changed(const int32_t* cls, int32_t* prev, int n, int* count, hipStream_t st);
 

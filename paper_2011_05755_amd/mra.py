@@ -25,7 +25,7 @@ DEFAULT_RESCORE_ROWS = 4
 
 EXPORTS = (
     "mra_create", "mra_destroy", "mra_load_refs", "mra_check_geom", "mra_unload_refs", "mra_refset_info",
-    "mra_align", "mra_update_averages", "mra_classify", "mra_rfa", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
+    "mra_align", "mra_align_noalloc", "mra_update_averages", "mra_classify", "mra_rfa", "mra_align_batch", "mra_set_tuning", "mra_get_tuning",
     "mra_debug_polar",
     "mra_debug_spectra", "mra_debug_cctable", "mra_debug_refs", "mra_profile", "mra_profile_read",
     "mra_last_error", "mra_strerror",
@@ -78,6 +78,7 @@ def load_library() -> ctypes.CDLL:
         "mra_unload_refs": [vp, i32],
         "mra_refset_info": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(Geom)],
         "mra_align": [vp, i32, vp, i64, ctypes.POINTER(Result)],
+        "mra_align_noalloc": [vp, i32, vp, i64, ctypes.POINTER(Result)],
         "mra_update_averages": [vp, i32, vp, i64, ctypes.POINTER(Result), vp, vp],
         "mra_classify": [vp, i32, ctypes.POINTER(Geom), vp, i64, vp, i32, i32, ctypes.c_double,
                          ctypes.POINTER(Result), vp, ctypes.POINTER(i32), ctypes.POINTER(i64)],
@@ -276,6 +277,18 @@ class Context:
         _check_result(out, N, parts.device)
         res = out.c_struct()
         self._check(self.lib.mra_align(self._h, refset_id, _ptr(parts), N, ctypes.byref(res)))
+        return out
+
+    def align_noalloc(self, refset_id: int, parts: torch.Tensor, out: AlignResult) -> AlignResult:
+        """mra_align_noalloc: as align, with the library's fixed device
+        scratch instead of its workspace; `out` must be given (nothing is
+        allocated by this call)."""
+        rs = self.refsets[refset_id]
+        _check_images(parts, rs.L, "parts")
+        N = parts.shape[0]
+        _check_result(out, N, parts.device)
+        res = out.c_struct()
+        self._check(self.lib.mra_align_noalloc(self._h, refset_id, _ptr(parts), N, ctypes.byref(res)))
         return out
 
     def align_batch(self, stacks: list[tuple[int, torch.Tensor, int, AlignResult]]):
