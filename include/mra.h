@@ -125,7 +125,8 @@ typedef struct mra_stack {
 
 /* Create a context on `device` whose work is enqueued on `hip_stream` (a
  * hipStream_t; NULL = the null stream).  `workspace_cap_bytes` bounds the
- * device workspace (0 = 8 GiB); large calls are split into chunks that fit. */
+ * device workspace (0 = 32 GiB); large calls are split into chunks that fit
+ * (larger chunks fill the GPU with longer correlation runs). */
 int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_cap_bytes);
 
 /* Free every refset and the workspace (synchronises the stream). */
@@ -265,12 +266,19 @@ int mra_align_batch(mra_ctx* ctx, const mra_stack* stacks, int32_t n);
  *                row, reference) pair whose upper bound on the CC (from its
  *                spectrum: exact magnitudes of the 32 lowest frequency slots,
  *                Cauchy-Schwarz over the energy of the rest) lies below the
- *                row's best so far, so it cannot win; 0: evaluate every pair.
+ *                best so far of the pair's row, or of any row of the same
+ *                particle, so it cannot win; 0: evaluate every pair.
+ *  run_tiles     consecutive 8-row tiles one correlation workgroup takes in
+ *                order, carrying each particle's best from one tile to the
+ *                next (longer runs prune more, shorter ones balance the
+ *                launch better); 0: chosen from the launch size (at most 8),
+ *                else 1..64.
  * Results do not depend on the tuning (bit for bit). */
 typedef struct mra_tuning {
   int32_t corr_variant;
   int32_t chunk_particles;
   int32_t prune;
+  int32_t run_tiles;
 } mra_tuning;
 int mra_set_tuning(mra_ctx* ctx, int32_t refset_id, const mra_tuning* t);
 int mra_get_tuning(mra_ctx* ctx, int32_t refset_id, mra_tuning* t);

@@ -351,33 +351,36 @@ struct Half16Contract {
 
 template <int NW>
 struct CorrSmem {
-  float* st;        // [128][2][64][2] spectra of the 64 (row, ref) pairs
+  float* st;                // [128][2][64][2] spectra of the 64 (row, ref) pairs
   float2* stc;
-  float* cand_v;    // [16][64]: per (wave, pass-2 row of the wave) and pair
-  int* cand_i;
-  float* pe;        // [NW][2][64] high-slot energy of each pair, per wave and p half
-  float2* pb;       // [NW][64] low-slot bound of each pair (both mirrors), per wave
-  int* list;        // [NW][64] each wave's list of the pairs that need the inverse FFT
-  float* rb_v;      // [8] running best per row
-  int* rb_i;
-  float2* tw;       // exp(-2 pi i e / 256)
-  int* item;        // batch work item broadcast
+  unsigned long long* key;  // [8] best candidate of each row so far (ordered key, 0 = none)
+  float* pe;                // [2][NW][2][64] high-slot energy per (reference-tile parity, wave, p half, pair)
+  float2* pb;               // [2][NW][64] low-slot bound of each pair (both mirrors), per parity and wave
+  int* list;                // [NW][64] each wave's list of the pairs that need the inverse FFT
+  float* thr;               // [8] each row's best before this reference tile's inverse FFT
+  float* pt;                // [8] best over the rows of the row's particle (this tile and carried)
+  int* ppart;               // [8] particle of each row slot (-1 past the chunk)
+  float* carry_v;           // best of the particle that the run's next tile may continue
+  int* carry_p;             // that particle (-1: none)
+  float2* tw;               // exp(-2 pi i e / 256)
   __device__ __forceinline__ CorrSmem(float* smem) {
     st = smem;
     stc = reinterpret_cast<float2*>(smem);
-    cand_v = smem + kSlots * 2 * 64 * 2;
-    cand_i = reinterpret_cast<int*>(cand_v + 16 * 64);
-    pe = reinterpret_cast<float*>(cand_i + 16 * 64);
-    pb = reinterpret_cast<float2*>(pe + 2 * NW * 64);
-    list = reinterpret_cast<int*>(pb + NW * 64);
-    rb_v = reinterpret_cast<float*>(list + NW * 64);
-    rb_i = reinterpret_cast<int*>(rb_v + 8);
-    tw = reinterpret_cast<float2*>(rb_i + 8);
-    item = reinterpret_cast<int*>(tw + kNphi);
+    key = reinterpret_cast<unsigned long long*>(smem + kSlots * 2 * 64 * 2);
+    pe = reinterpret_cast<float*>(key + 8);
+    pb = reinterpret_cast<float2*>(pe + 2 * NW * 2 * 64);
+    list = reinterpret_cast<int*>(pb + 2 * NW * 64);
+    thr = reinterpret_cast<float*>(list + NW * 64);
+    pt = thr + 8;
+    ppart = reinterpret_cast<int*>(pt + 8);
+    carry_v = reinterpret_cast<float*>(ppart + 8);
+    carry_p = reinterpret_cast<int*>(carry_v + 2);
+    tw = reinterpret_cast<float2*>(carry_p + 2);
   }
   static constexpr size_t bytes() {
-    return (size_t)kSlots * 2 * 64 * 2 * sizeof(float) + 2 * 16 * 64 * sizeof(float) +
-           5 * NW * 64 * sizeof(float) + 16 * sizeof(float) + kNphi * sizeof(float2) + 4 * sizeof(int);
+    return (size_t)kSlots * 2 * 64 * 2 * sizeof(float) + 8 * sizeof(unsigned long long) +
+           2 * NW * 2 * 64 * sizeof(float) + 2 * NW * 64 * sizeof(float2) + NW * 64 * sizeof(int) +
+           8 * sizeof(float) * 2 + 8 * sizeof(int) + 2 * sizeof(float) + 2 * sizeof(int) + kNphi * sizeof(float2);
   }
 };
 
@@ -390,21 +393,35 @@ template <int O>
 __device__ __forceinline__ float ror16f(float v) {
   return __int_as_float(ror16<O>(__float_as_int(v)));
 }
-// (v, i) := the better of itself and the lane O further on in its row of 16
-template <int O>
-__device__ __forceinline__ void better_ror(float& v, int& i) {
-  const float v2 = ror16f<O>(v);
-  const int i2 = ror16<O>(i);
-  if (better(v2, i2, v, i)) {
-    v = v2;
-    i = i2;
-  }
-}
 
 __device__ __forceinline__ void lds_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A candidate (CC value v, flat index iota < 2^31 - 1) as one 64-bit key whose
+// unsigned order is the arg-max order: larger v first, then smaller iota.  0
+// is below every candidate.
+__device__ __forceinline__ unsigned long long cand_key(float v, int iota) {
+  const uint32_t u = __float_as_uint(v == 0.f ? 0.f : v);  // -0 ties with +0, as in the float order
+  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((unsigned long long)o << 32) | (unsigned long long)(0x7fffffffu - (uint32_t)iota);
+}
+__device__ __forceinline__ float key_value(unsigned long long k) {
+  if (k == 0ull) return -INFINITY;
+  const uint32_t o = (uint32_t)(k >> 32);
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+__device__ __forceinline__ int key_index(unsigned long long k) {
+  return k == 0ull ? 0x7fffffff : (int)(0x7fffffffu - (uint32_t)k);
+}
+
+// The pruning threshold a particle's best so far imposes on its rows: the
+// best itself, or (re-ranked 16-bit forms) margin * |best| below it, so that
+// every row within that margin of the particle's best keeps its exact best.
+__device__ __forceinline__ float part_thr(float best, float margin) {
+  return (margin > 0.f && best > -INFINITY) ? best - margin * fabsf(best) : best;
 }
 
 // Power-of-two FP16 scale of chunk row r: |a +- b| <= 2 * 256 * max|pixel|
@@ -428,20 +445,32 @@ constexpr int kArgmax = 0, kTable = 1, kRunnerUp = 2;
 // with the terms of slots below kLowSlots taken exactly from the spectra and
 // the rest bounded by Cauchy-Schwarz through the pairs' high-slot energy
 // (sum of 2|G_m,f| <= sqrt(2 * 96 * sum of the squared MFMA entries)).  A pair
-// whose bound, inflated by 2^-12 against rounding, is below the row's best
-// over earlier reference tiles cannot win (a tie with an earlier tile loses
-// on the flat index), so its inverse FFT and arg-max are skipped.  The live
-// pairs are packed into the lanes of each wave: a pass takes
-// ceil(CPW * live / 64) steps instead of CPW (CPW = 16 / NW columns or rows
-// per wave).  Results are identical with and without pruning.
+// whose bound, inflated by 2^-12 against rounding, is below the threshold of
+// its row cannot matter, so its inverse FFT and arg-max are skipped.  The
+// threshold is the larger of the row's own best over earlier reference tiles
+// (a tie with it loses on the flat index) and the best over every row of the
+// same particle seen so far, in this tile and in the earlier tiles of the
+// workgroup's run (part_thr: minus a.margin of it for the re-ranked 16-bit
+// forms).  A row's reported best is exact whenever it reaches that particle
+// threshold, so the particle's winner (and, with a margin, every row the
+// re-ranking considers) is the same with and without pruning.  Most pairs of
+// a particle's later tiles fall below it, and a reference tile with no live
+// pair skips the inverse FFT and its barriers altogether.
 template <int PREC, int NW, class Contract, int MODE, bool SPLIT>
 __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const CorrSmem<NW>& sm, Contract& con) {
   constexpr int CPW = 16 / NW;  // inverse-FFT columns (pass 1) and rows (pass 2) per wave
-  const int tid = threadIdx.x, ln = tid & 63;
+  // the lane index is opaque in every tile, so that nothing derived from it
+  // is hoisted out of the run's tile loop and kept live across it
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int ln = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < 8) {
-    sm.rb_v[tid] = -INFINITY;
-    sm.rb_i[tid] = 0x7fffffff;
+    const int row = tile * kRowTile + tid;
+    const int part = row < a.rows ? row / a.S : -1;
+    sm.key[tid] = 0ull;
+    sm.ppart[tid] = part;
+    sm.pt[tid] = (part >= 0 && part == *sm.carry_p) ? *sm.carry_v : -INFINITY;
   }
   // FP16: the lane's operand row (ln & 7) is scaled by a power of two of its
   // particle (exact, so results do not depend on how particles are grouped)
@@ -456,6 +485,8 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
   bool prune = MODE != kTable && NW == 8 && a.prune;
 
   for (int kt = 0; kt < a.n_ref_tiles; ++kt) {
+    const int par = kt & 1;  // energy and bound partials alternate, so a wave may write the next
+                             // tile's while another still reads this one's
     // ---------------- contraction on the matrix cores ----------------
     con.run(a, sm.st, tile, kt, w, ln);
     if (prune) {
@@ -468,7 +499,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
       if ((ln & 8) == 0) {
         const int ref = ln & 7, row0 = ((ln >> 4) & 1) * 4, p = ln >> 5;
 #pragma unroll
-        for (int i2 = 0; i2 < 4; ++i2) sm.pe[(w * 2 + p) * 64 + (row0 + i2) * 8 + ref] = e[i2];
+        for (int i2 = 0; i2 < 4; ++i2) sm.pe[((par * NW + w) * 2 + p) * 64 + (row0 + i2) * 8 + ref] = e[i2];
       }
       // exact terms of the wave's own low slots (written by this wave)
       lds_wave_sync();
@@ -489,9 +520,13 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
           b1 += sqrtf(s2 * s2 + d1 * d1);
         }
       }
-      sm.pb[w * 64 + P] = make_float2(b0, b1);
+      sm.pb[(par * NW + w) * 64 + P] = make_float2(b0, b1);
     }
     __syncthreads();
+    // each row's best before this tile's candidates arrive: candidates of this
+    // tile are recorded only above it (equal values of earlier tiles have
+    // smaller flat indices)
+    if (MODE != kTable && tid < 8) sm.thr[tid] = key_value(sm.key[tid]);
 
     // ---------------- which pairs need the inverse FFT ----------------
     uint64_t live = ~0ull;
@@ -500,19 +535,21 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
       float B0 = 0.f, B1 = 0.f, E = 0.f;
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) {
-        const float2 b = sm.pb[w2 * 64 + P];
+        const float2 b = sm.pb[(par * NW + w2) * 64 + P];
         B0 += b.x;
         B1 += b.y;
-        E += sm.pe[(w2 * 2) * 64 + P] + sm.pe[(w2 * 2 + 1) * 64 + P];
+        E += sm.pe[((par * NW + w2) * 2) * 64 + P] + sm.pe[((par * NW + w2) * 2 + 1) * 64 + P];
       }
       const float bound = (a.M == 2 ? fmaxf(B0, B1) : B0) + sqrtf(2.f * (kSlots - kLowSlots) * E);
       const int row_l = P >> 3, ref_l = P & 7;
+      const float thr = fmaxf(key_value(sm.key[row_l]), part_thr(sm.pt[row_l], a.margin));
       const bool keep = tile * kRowTile + row_l < a.rows && kt * kRefTile + ref_l < a.K &&
-                        !(bound * (1.f + 1.f / 4096.f) < sm.rb_v[row_l]);
+                        !(bound * (1.f + 1.f / 4096.f) < thr);
       live = __ballot(keep);
     }
     const int n_live = __popcll(live);
     if (prune && kt >= 2 && n_live > 56) prune = false;  // wave-uniform
+    if (n_live == 0) continue;  // workgroup-uniform: every wave read the same partials
     {
       const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0));
       if ((live >> ln) & 1) list[rank] = ln;
@@ -559,231 +596,132 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     // so that either keeps its 16 reads at constant offsets from one address
     // (in one loop the compiler merges the two read sets into 31 per-element
     // addresses); the 4-wave kernels, whose registers are full, keep one loop.
+    auto pass2 = [&](auto dir_c) {
+      constexpr int dir = decltype(dir_c)::value;  // 1 up, 2 down, 0 either (chosen per wave)
+#pragma unroll 1
+      for (int n0 = 0; n0 < n_live; n0 += LPC) {
+        int lnx = ln;
+        asm volatile("" : "+v"(lnx));
+        const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
+        const bool act = n0 + lane_n < n_live;
+        const int P = list[act ? n0 + lane_n : 0];
+        const int row_l = P >> 3, ref_l = P & 7;
+        const int row = tile * kRowTile + row_l;
+        const int k = kt * kRefTile + ref_l;
+        float2 x[16];
+        const bool low = dir == 1 || (dir == 0 && CPW * w < 8);
+        if (low) {
+          const int base = n1 * 2048 + P;
+#pragma unroll
+          for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
+        } else if constexpr (dir == 2) {
+          const int base = (513 - 32 * n1) * 64 + P;  // k2 = 0; k2 steps go down by 128
+          int top = base - 15 * 128;                  // k2 = 15, the lowest address
+          asm volatile("" : "+v"(top));               // the base of the reads (not re-associated)
+          x[0] = sm.stc[n1 == 8 ? 64 + P : base];
+#pragma unroll
+          for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[top + (15 - k2) * 128];
+        } else {
+          const int base = (513 - 32 * n1) * 64 + P;
+          x[0] = sm.stc[n1 == 8 ? 64 + P : base];
+#pragma unroll
+          for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
+        }
+        inv_pass2(x);
+        if constexpr (MODE == kTable) {
+          if (act && row < a.rows && k < a.K) {
+            const int n = row / a.S, s = row - n * a.S;
+            const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
+            for (int m = 0; m < a.M; ++m) {
+              float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
+#pragma unroll
+              for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
+            }
+          }
+        } else {
+          // only values above the row's best of earlier reference tiles can
+          // win (a tie with an earlier tile loses: its flat index is smaller)
+          const float thr = sm.thr[row_l];
+          const bool valid = act && row < a.rows && k < a.K;
+          // the candidate left out of this pass (key m * 256 + angle of this
+          // lane's (row, ref)), or -1
+          int ex = -1;
+          if (MODE == kRunnerUp && valid) {
+            const int n = row / a.S, s = row - n * a.S;
+            const int e = a.excl[n];
+            if (e >= 0) {
+              const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
+              if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
+            }
+          }
+          float bv = -INFINITY;
+          int bi = 0x7fffffff;
+          float mx = -INFINITY;
+#pragma unroll
+          for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
+          if (MODE == kArgmax && mx > thr) {
+            // the lane's best is mx; its key is the smallest among the
+            // candidates equal to it (keys grow with n2, mirror 1 after 0)
+            bv = mx;
+            if (a.M == 2) {
+#pragma unroll
+              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
+            }
+#pragma unroll
+            for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
+          } else if (MODE == kRunnerUp && mx > thr) {
+#pragma unroll
+            for (int n2 = 0; n2 < 16; ++n2) {
+              const int ang = n1 + 16 * n2;
+              if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+              if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
+                bv = x[n2].y;
+                bi = 256 + ang;
+              }
+            }
+          }
+          if (valid && bi != 0x7fffffff && bv > thr) {
+            const int iota = ((k * a.M + (bi >> 8)) * a.S + row % a.S) * kNphi + (bi & 255);
+            atomicMax(&sm.key[row_l], cand_key(bv, iota));
+          }
+        }
+      }
+    };
     if constexpr (SPLIT) {
-      {
-        auto pass2 = [&](auto dir_c) {
-        constexpr bool low = decltype(dir_c)::value == 1;  // 1 up, 2 down
-#pragma unroll 1
-        for (int n0 = 0; n0 < n_live; n0 += LPC) {
-          int lnx = ln;
-          asm volatile("" : "+v"(lnx));
-          const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
-          const bool act = n0 + lane_n < n_live;
-          const int P = list[act ? n0 + lane_n : 0];
-          const int row_l = P >> 3, ref_l = P & 7;
-          const int row = tile * kRowTile + row_l;
-          const int k = kt * kRefTile + ref_l;
-          float2 x[16];
-          if constexpr (low) {
-            const int base = n1 * 2048 + P;
-#pragma unroll
-            for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
-          } else {
-            const int base = (513 - 32 * n1) * 64 + P;  // k2 = 0; k2 steps go down by 128
-            int top = base - 15 * 128;                  // k2 = 15, the lowest address
-            asm volatile("" : "+v"(top));               // the base of the reads (not re-associated)
-            x[0] = sm.stc[n1 == 8 ? 64 + P : base];
-#pragma unroll
-            for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[top + (15 - k2) * 128];
-          }
-          inv_pass2(x);
-          if constexpr (MODE == kTable) {
-            if (act && row < a.rows && k < a.K) {
-              const int n = row / a.S, s = row - n * a.S;
-              const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
-              for (int m = 0; m < a.M; ++m) {
-                float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
-#pragma unroll
-                for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
-              }
-            }
-          } else {
-            // only values above the row's best of earlier reference tiles can
-            // win (a tie with an earlier tile loses: its flat index is smaller)
-            const float thr = sm.rb_v[row_l];
-            // the candidate left out of this pass (key m * 256 + angle of this
-            // lane's (row, ref)), or -1
-            int ex = -1;
-            if (MODE == kRunnerUp && row < a.rows && k < a.K) {
-              const int n = row / a.S, s = row - n * a.S;
-              const int e = a.excl[n];
-              if (e >= 0) {
-                const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
-                if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
-              }
-            }
-            float bv = -INFINITY;
-            int bi = 0x7fffffff;
-            float mx = -INFINITY;
-#pragma unroll
-            for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
-            if (MODE == kArgmax && mx > thr) {
-              // the lane's best is mx; its key is the smallest among the
-              // candidates equal to it (keys grow with n2, mirror 1 after 0)
-              bv = mx;
-              if (a.M == 2) {
-#pragma unroll
-                for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
-              }
-#pragma unroll
-              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
-            } else if (MODE == kRunnerUp && mx > thr) {
-#pragma unroll
-              for (int n2 = 0; n2 < 16; ++n2) {
-                const int ang = n1 + 16 * n2;
-                if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
-                if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
-                  bv = x[n2].y;
-                  bi = 256 + ang;
-                }
-              }
-            }
-            if (act) {
-              sm.cand_v[(w * CPW + c) * 64 + P] = bv;
-              sm.cand_i[(w * CPW + c) * 64 + P] = bi;
-            }
-          }
-        }
-        };
-        if (CPW * w < 8) pass2(std::integral_constant<int, 1>{});  // wave-uniform
-        else pass2(std::integral_constant<int, 2>{});
-      }
+      if (CPW * w < 8) pass2(std::integral_constant<int, 1>{});  // wave-uniform
+      else pass2(std::integral_constant<int, 2>{});
     } else {
-      {
-        const bool low = CPW * w < 8;  // wave-uniform
-#pragma unroll 1
-        for (int n0 = 0; n0 < n_live; n0 += LPC) {
-          int lnx = ln;
-          asm volatile("" : "+v"(lnx));
-          const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
-          const bool act = n0 + lane_n < n_live;
-          const int P = list[act ? n0 + lane_n : 0];
-          const int row_l = P >> 3, ref_l = P & 7;
-          const int row = tile * kRowTile + row_l;
-          const int k = kt * kRefTile + ref_l;
-          float2 x[16];
-          if (low) {
-            const int base = n1 * 2048 + P;
-#pragma unroll
-            for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
-          } else {
-            const int base = (513 - 32 * n1) * 64 + P;
-            x[0] = sm.stc[n1 == 8 ? 64 + P : base];
-#pragma unroll
-            for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
-          }
-          inv_pass2(x);
-          if constexpr (MODE == kTable) {
-            if (act && row < a.rows && k < a.K) {
-              const int n = row / a.S, s = row - n * a.S;
-              const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
-              for (int m = 0; m < a.M; ++m) {
-                float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
-#pragma unroll
-                for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
-              }
-            }
-          } else {
-            // only values above the row's best of earlier reference tiles can
-            // win (a tie with an earlier tile loses: its flat index is smaller)
-            const float thr = sm.rb_v[row_l];
-            // the candidate left out of this pass (key m * 256 + angle of this
-            // lane's (row, ref)), or -1
-            int ex = -1;
-            if (MODE == kRunnerUp && row < a.rows && k < a.K) {
-              const int n = row / a.S, s = row - n * a.S;
-              const int e = a.excl[n];
-              if (e >= 0) {
-                const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
-                if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
-              }
-            }
-            float bv = -INFINITY;
-            int bi = 0x7fffffff;
-            float mx = -INFINITY;
-#pragma unroll
-            for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
-            if (MODE == kArgmax && mx > thr) {
-              // the lane's best is mx; its key is the smallest among the
-              // candidates equal to it (keys grow with n2, mirror 1 after 0)
-              bv = mx;
-              if (a.M == 2) {
-#pragma unroll
-                for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
-              }
-#pragma unroll
-              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
-            } else if (MODE == kRunnerUp && mx > thr) {
-#pragma unroll
-              for (int n2 = 0; n2 < 16; ++n2) {
-                const int ang = n1 + 16 * n2;
-                if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
-                if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
-                  bv = x[n2].y;
-                  bi = 256 + ang;
-                }
-              }
-            }
-            if (act) {
-              sm.cand_v[(w * CPW + c) * 64 + P] = bv;
-              sm.cand_i[(w * CPW + c) * 64 + P] = bi;
-            }
-          }
-        }
-      }
+      pass2(std::integral_constant<int, 0>{});
     }
     __syncthreads();
-    if constexpr (MODE != kTable) {
-      // waves reduce the 8 rows: lane = (wave of origin, ref)
-      for (int r = w; r < kRowTile; r += NW) {
-        if (((live >> (r * 8)) & 0xff) == 0) continue;  // no pair of the row can win
-        const int ww = ln >> 3, ref = ln & 7;
-        const int P = r * 8 + ref;
-        const int rr = tile * kRowTile + r;
-        const int kk = kt * kRefTile + ref;
-        float v = -INFINITY;
-        int iota = 0x7fffffff;
-        if ((live >> P) & 1) {
-          for (int w2 = ww; w2 < NW; w2 += 8) {
+    // the particle bests of the rows, for the next reference tile's bound
+    if (MODE != kTable && tid < 8) {
+      float b = sm.pt[tid];
+      const int part = sm.ppart[tid];
 #pragma unroll
-            for (int c = 0; c < CPW; ++c) {
-              const float v2 = sm.cand_v[(w2 * CPW + c) * 64 + P];
-              const int li = sm.cand_i[(w2 * CPW + c) * 64 + P];
-              if (li != 0x7fffffff && kk < a.K && rr < a.rows) {
-                const int m = li >> 8, ang = li & 255;
-                const int i2 = ((kk * a.M + m) * a.S + rr % a.S) * kNphi + ang;
-                if (better(v2, i2, v, iota)) { v = v2; iota = i2; }
-              }
-            }
-          }
-        }
-        // best over each row of 16 lanes (DPP), then over the four rows
-        better_ror<8>(v, iota);
-        better_ror<4>(v, iota);
-        better_ror<2>(v, iota);
-        better_ror<1>(v, iota);
-        float bv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-        int bi = __builtin_amdgcn_readlane(iota, 0);
-#pragma unroll
-        for (int l0 = 16; l0 < 64; l0 += 16) {
-          const float v2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l0));
-          const int i2 = __builtin_amdgcn_readlane(iota, l0);
-          if (better(v2, i2, bv, bi)) { bv = v2; bi = i2; }
-        }
-        if (ln == 0 && bi != 0x7fffffff && better(bv, bi, sm.rb_v[r], sm.rb_i[r])) {
-          sm.rb_v[r] = bv;
-          sm.rb_i[r] = bi;
-        }
-      }
+      for (int r = 0; r < kRowTile; ++r)
+        if (sm.ppart[r] == part) b = fmaxf(b, key_value(sm.key[r]));
+      sm.pt[tid] = b;
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (MODE != kTable && tid < 8) {
     const int r = tile * kRowTile + tid;
     if (r < a.rows) {
+      const unsigned long long kk = sm.key[tid];
       const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, r) * a.b_scale) : 1.f;
-      a.row_cc[r] = sm.rb_v[tid] * unscale;
-      a.row_idx[r] = sm.rb_i[tid];
+      a.row_cc[r] = key_value(kk) * unscale;
+      a.row_idx[r] = key_index(kk);
+    }
+    // the particle of the last row continues into the run's next tile
+    float b = sm.pt[tid];
+    const int part = sm.ppart[tid];
+#pragma unroll
+    for (int r2 = 0; r2 < kRowTile; ++r2)
+      if (sm.ppart[r2] == part) b = fmaxf(b, key_value(sm.key[r2]));
+    if (tid == 7) {
+      *sm.carry_p = part;
+      *sm.carry_v = b;
     }
   }
 }
@@ -794,39 +732,39 @@ struct ContractFor {
                                     Half16Contract<PREC == kFP32 ? kBF16 : PREC, NW, MAXR, EXACT, RES>>::type type;
 };
 
+// Row tiles of run `run` (a.tiles_per_run consecutive tiles), in order, so
+// that a particle's best carries from one of its tiles to the next.
+template <int PREC, int NW, class Contract, int MODE, bool SPLIT>
+__device__ __forceinline__ void corr_run(const CorrArgs& a, int run, const CorrSmem<NW>& sm, Contract& con) {
+  const int t0 = run * a.tiles_per_run;
+  const int t1 = min(t0 + a.tiles_per_run, a.n_row_tiles);
+  if (threadIdx.x == 0) *sm.carry_p = -1;
+  lds_wave_sync();
+  for (int t = t0; t < t1; ++t) corr_tile<PREC, NW, Contract, MODE, SPLIT>(a, t, sm, con);
+}
+
 template <int PREC, int NW, int MAXR, bool RES, bool EXACT, int MODE>
 __global__ __launch_bounds__(NW * 64) void k_corr(CorrArgs a) {
   extern __shared__ float smem[];
   CorrSmem<NW> sm(smem);
   if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(a.cs32, threadIdx.x);
   typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
-  corr_tile<PREC, NW, decltype(con), MODE, NW == 8>(a, blockIdx.x, sm, con);
+  corr_run<PREC, NW, decltype(con), MODE, NW == 8>(a, blockIdx.x, sm, con);
 }
 
-// Persistent form over the row tiles of several stacks.  Workgroup g takes
-// item g first, then items gridDim.x + counter++ until all are done; the
-// next item is requested while the current one runs, so the counter's
-// latency is hidden.  Every workgroup exits once an item is past the end
-// (the counter only grows), and *counter must be 0 at launch.
+// Batched form over the runs of several stacks' row tiles: workgroup g takes
+// run g of the concatenated run list (run_start[p] is piece p's first).
 template <int PREC, int NW, int MAXR, bool RES, bool EXACT>
 __global__ __launch_bounds__(NW * 64) void k_corr_batch(CorrBatch b) {
   extern __shared__ float smem[];
   CorrSmem<NW> sm(smem);
   if (threadIdx.x < kNphi) sm.tw[threadIdx.x] = w256c(b.piece[0].cs32, threadIdx.x);
   typename ContractFor<PREC, NW, MAXR, RES, EXACT>::type con;
-  const int total = b.tile_start[b.n];
-  int item = blockIdx.x;
-  while (item < total) {
-    int next = 0;
-    if (threadIdx.x == 0) next = atomicAdd(b.counter, 1) + (int)gridDim.x;
-    int p = 0;
-    while (p + 1 < b.n && b.tile_start[p + 1] <= item) ++p;
-    corr_tile<PREC, NW, decltype(con), kArgmax, NW == 8>(b.piece[p], item - b.tile_start[p], sm, con);
-    if (threadIdx.x == 0) *sm.item = next;
-    __syncthreads();
-    item = *sm.item;
-    __syncthreads();
-  }
+  const int item = blockIdx.x;
+  if (item >= b.run_start[b.n]) return;
+  int p = 0;
+  while (p + 1 < b.n && b.run_start[p + 1] <= item) ++p;
+  corr_run<PREC, NW, decltype(con), kArgmax, NW == 8>(b.piece[p], item - b.run_start[p], sm, con);
 }
 
 template <int P_, int NW_, int MR_, bool RES_, bool EXACT_>
@@ -837,7 +775,8 @@ struct Cfg {
 
 template <class C, int MODE>
 inline void launch_mode(const CorrArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, MODE>), dim3(a.n_row_tiles), dim3(C::NW * 64),
+  const int runs = (a.n_row_tiles + a.tiles_per_run - 1) / a.tiles_per_run;
+  hipLaunchKernelGGL((k_corr<C::P, C::NW, C::MR, C::RES, C::EXACT, MODE>), dim3(runs), dim3(C::NW * 64),
                      CorrSmem<C::NW>::bytes(), st, a);
 }
 
@@ -849,8 +788,9 @@ inline void launch_one(const CorrArgs& a, bool table, hipStream_t st) {
 
 template <class C>
 inline void launch_one(const CorrBatch& b, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_corr_batch<C::P, C::NW, C::MR, C::RES, C::EXACT>), dim3(grid), dim3(C::NW * 64),
-                     CorrSmem<C::NW>::bytes(), st, b);
+  (void)grid;
+  hipLaunchKernelGGL((k_corr_batch<C::P, C::NW, C::MR, C::RES, C::EXACT>), dim3(b.run_start[b.n]),
+                     dim3(C::NW * 64), CorrSmem<C::NW>::bytes(), st, b);
 }
 
 // Per-precision instantiation sets (one translation unit each).  `b` null:

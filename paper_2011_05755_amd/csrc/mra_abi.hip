@@ -52,6 +52,7 @@ struct Refset {
   int variant = 0;         // correlation kernel tile configuration
   int chunk = 0;           // particles per chunk (0: from the workspace cap)
   int prune = 1;           // exact pruning of the inverse FFT in the correlation kernel
+  int run_tiles = 0;       // row tiles per correlation workgroup (0: from the launch size)
 };
 
 struct Fail {
@@ -72,7 +73,6 @@ struct mra_ctx {
   float2* cs32 = nullptr;
   std::map<std::string, DevBuf> ws;
   int n_cu = 256;
-  int* counter = nullptr;  // work-item counter of persistent launches
   void* scratch = nullptr; // this device's copy of the no-allocation scratch
   bool profiling = false;
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
@@ -410,6 +410,8 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.row_idx = ridx;
   ca.table = table;
   ca.prune = rs.prune;
+  ca.tiles_per_run = table ? 1 : (rs.run_tiles > 0 ? rs.run_tiles : corr_tiles_per_run(tiles, c->n_cu));
+  ca.margin = (rs.g.precision != kFP32 && rs.g.rescore_rows >= 2) ? kRerankMargin : 0.f;
   timed(c, "corr", [&] { hip_check(c, launch_corr(rs.g.precision, rs.variant, table != nullptr, ca, st), "corr"); });
   if (table) return;
 
@@ -553,8 +555,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
   MergeBatch mb{};
   RescoreBatch rb{};
   pb.n = cb.n = mb.n = rb.n = (int)w.size();
-  cb.counter = c->counter;
-  int part = 0, tile = 0;
+  int part = 0, run = 0;
   for (size_t i = 0; i < w.size(); ++i) {
     const Piece& pc = w[i];
     const Refset& rs = *pc.rs;
@@ -585,7 +586,9 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = pc.p.S; ca.M = pc.p.M;
     ca.maxabs = mx; ca.b_scale = rs.b_scale; ca.cs32 = c->cs32;
     ca.row_cc = rcc + pc.row0; ca.row_idx = ridx + pc.row0; ca.table = nullptr; ca.prune = rs.prune;
-    cb.tile_start[i] = tile;
+    ca.tiles_per_run = rs.run_tiles > 0 ? rs.run_tiles : corr_tiles_per_run(ptiles, c->n_cu);
+    ca.margin = (prec != kFP32 && rs.g.rescore_rows >= 2) ? kRerankMargin : 0.f;
+    cb.run_start[i] = run;
 
     MergeArgs& ma = mb.piece[i];
     ma.row_cc = rcc + pc.row0; ma.row_idx = ridx + pc.row0;
@@ -608,13 +611,12 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     rb.start[i] = part;
 
     part += pc.nc;
-    tile += ptiles;
+    run += (ptiles + ca.tiles_per_run - 1) / ca.tiles_per_run;
   }
   pb.start[w.size()] = mb.start[w.size()] = rb.start[w.size()] = part;
-  cb.tile_start[w.size()] = tile;
+  cb.run_start[w.size()] = run;
   timed(c, "polar", [&] { hip_check(c, launch_polar_batch(pb, st), "polar batch"); });
-  hip_check(c, hipMemsetAsync(c->counter, 0, sizeof(int), st), "memset");
-  const int grid = std::min(tile, c->n_cu);
+  const int grid = run;
   timed(c, "corr", [&] { hip_check(c, launch_corr_batch(prec, variant, cb, grid, st), "corr batch"); });
   timed(c, "merge", [&] { hip_check(c, launch_merge_batch(mb, st), "merge batch"); });
   if (prec != kFP32) timed(c, "rescore", [&] { hip_check(c, launch_rescore_batch(rb, st), "rescore batch"); });
@@ -803,12 +805,13 @@ void iterate_impl(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts,
                   int32_t K, int32_t max_iter, double max_changed_frac, const mra_result* out, int32_t* counts,
                   int32_t* n_iter, int64_t* changed, bool by_flat) {
   // a tuning set on this refset id carries over when the geometry matches
-  int variant = -1, chunk = 0, prune = 1;
+  int variant = -1, chunk = 0, prune = 1, run_tiles = 0;
   auto old = c->refs.find(id);
   if (old != c->refs.end() && old->second.K == K && std::memcmp(&old->second.g, g, sizeof(mra_geom)) == 0) {
     variant = old->second.variant;
     chunk = old->second.chunk;
     prune = old->second.prune;
+    run_tiles = old->second.run_tiles;
   }
   hipStream_t st = c->stream;
   mra_result o = *out;
@@ -824,6 +827,7 @@ void iterate_impl(mra_ctx* c, int32_t id, const mra_geom* g, const float* parts,
       rs.variant = variant;
       rs.chunk = chunk;
       rs.prune = prune;
+      rs.run_tiles = run_tiles;
     }
     align_impl(c, id, parts, N, -1, &o, nullptr);
     int64_t n_changed = N;
@@ -895,7 +899,7 @@ int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_c
   if (!c) return MRA_E_NOMEM;
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  c->cap = workspace_cap_bytes ? workspace_cap_bytes : (8ull << 30);
+  c->cap = workspace_cap_bytes ? workspace_cap_bytes : (32ull << 30);
   int rc = guard(c, [&] {
     std::vector<double> cs, sn;
     build_cs(kNphi, cs, sn);
@@ -909,7 +913,6 @@ int mra_create(mra_ctx** out, int device, void* hip_stream, uint64_t workspace_c
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
       c->n_cu = ncu;
     c->scratch = scratch_ptr(c);
-    c->counter = (int*)alloc(c, 256, "counter");
     c->cs64 = (double2*)alloc(c, kNphi * sizeof(double2), "cs64");
     c->cs32 = (float2*)alloc(c, kNphi * sizeof(float2), "cs32");
     hip_check(c, hipMemcpy(c->cs64, h64.data(), kNphi * sizeof(double2), hipMemcpyHostToDevice), "memcpy");
@@ -931,7 +934,6 @@ int mra_destroy(mra_ctx* c) {
   for (auto& kv : c->refs) free_refset(kv.second);
   for (auto& kv : c->ws)
     if (kv.second.p) (void)hipFree(kv.second.p);
-  if (c->counter) (void)hipFree(c->counter);
   if (c->cs64) (void)hipFree(c->cs64);
   if (c->cs32) (void)hipFree(c->cs32);
   delete c;
@@ -1089,9 +1091,11 @@ int mra_set_tuning(mra_ctx* c, int32_t id, const mra_tuning* t) {
     if (!corr_variant_ok(rs.g.precision, v, rs.R4)) throw Fail{MRA_E_INVAL, "variant cannot serve this geometry"};
     if (t->chunk_particles < 0) throw Fail{MRA_E_INVAL, "chunk_particles must be >= 0"};
     if (t->prune < -1 || t->prune > 1) throw Fail{MRA_E_INVAL, "prune must be -1, 0 or 1"};
+    if (t->run_tiles < 0 || t->run_tiles > 64) throw Fail{MRA_E_INVAL, "run_tiles must be in [0, 64]"};
     rs.variant = v;
     rs.chunk = t->chunk_particles;
     rs.prune = t->prune != 0;
+    rs.run_tiles = t->run_tiles;
   });
 }
 
@@ -1102,6 +1106,7 @@ int mra_get_tuning(mra_ctx* c, int32_t id, mra_tuning* t) {
     t->corr_variant = rs.variant;
     t->chunk_particles = rs.chunk;
     t->prune = rs.prune;
+    t->run_tiles = rs.run_tiles;
   });
 }
 

@@ -18,6 +18,11 @@ constexpr int kPolarThreads = 64 * kPolarWaves;
 constexpr int kMaxBatchPieces = 12; // stack pieces per batched launch (kernel-argument table)
 constexpr int kAvgChunk = 32;       // particles per partial class sum
 constexpr int kAvgThreads = 256;
+constexpr int kMaxRunTiles = 8;     // consecutive row tiles per correlation workgroup (a run)
+// Re-ranked 16-bit forms: the rows whose 16-bit best lies within this
+// fraction of the particle's best are the re-ranking candidates (and keep
+// their exact best under pruning).
+constexpr float kRerankMargin = 1.f / 128.f;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
@@ -82,15 +87,17 @@ struct CorrArgs {
   int* row_idx;          // [rows] flat index of the row's best
   float* table;          // debug: [n][K][M][S][256], else null
   const int* excl;       // per particle of the chunk: flat index left out of the arg-max, or null
-  int prune;             // 1: skip the inverse FFT of pairs whose CC bound is below the row's best
+  int prune;             // 1: skip the inverse FFT of pairs whose CC bound is below the row's threshold
+  int tiles_per_run;     // consecutive row tiles per workgroup (>= 1)
+  float margin;          // particle threshold: best - margin * |best| (0: the best itself)
 };
 
-// Batched correlation: pieces of several stacks in one persistent launch.
-// tile_start[i] is the first work item of piece i; tile_start[n] the total.
+// Batched correlation: pieces of several stacks in one launch, one
+// workgroup per run of row tiles.  run_start[i] is the first run of piece i;
+// run_start[n] the total.
 struct CorrBatch {
   int n;
-  int* counter;          // zeroed before the launch
-  int tile_start[kMaxBatchPieces + 1];
+  int run_start[kMaxBatchPieces + 1];
   CorrArgs piece[kMaxBatchPieces];
 };
 
@@ -163,6 +170,13 @@ size_t polar_lds_bytes(int Lp);
 hipError_t launch_corr(int prec, int variant, bool table, const CorrArgs& a, hipStream_t st);
 hipError_t launch_corr_runner_up(int prec, const CorrArgs& a, hipStream_t st);
 hipError_t launch_corr_batch(int prec, int variant, const CorrBatch& b, int grid, hipStream_t st);
+// row tiles per correlation run for a launch of `tiles` tiles on n_cu CUs:
+// long runs carry each particle's best across its tiles, enough runs keep
+// every CU busy
+inline int corr_tiles_per_run(int tiles, int n_cu) {
+  const int g = tiles / (3 * (n_cu > 0 ? n_cu : 1));
+  return g < 1 ? 1 : (g > kMaxRunTiles ? kMaxRunTiles : g);
+}
 bool corr_variant_ok(int prec, int variant, int R4);
 int corr_default_variant(int prec, int R4);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t st);

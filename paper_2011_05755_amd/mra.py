@@ -49,7 +49,8 @@ class Stack(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("corr_variant", ctypes.c_int32), ("chunk_particles", ctypes.c_int32), ("prune", ctypes.c_int32)]
+    _fields_ = [("corr_variant", ctypes.c_int32), ("chunk_particles", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("run_tiles", ctypes.c_int32)]
 
 
 class MRAError(RuntimeError):
@@ -375,8 +376,9 @@ class Context:
         return out, average, n_iter.value, list(changed[:n_iter.value])
 
     # ---- tile configuration (see include/mra.h, mra_tuning) ----
-    def set_tuning(self, refset_id: int, corr_variant: int = -1, chunk_particles: int = 0, prune: int = -1):
-        t = Tuning(corr_variant, chunk_particles, prune)
+    def set_tuning(self, refset_id: int, corr_variant: int = -1, chunk_particles: int = 0, prune: int = -1,
+                   run_tiles: int = 0):
+        t = Tuning(corr_variant, chunk_particles, prune, run_tiles)
         self._check(self.lib.mra_set_tuning(self._h, refset_id, ctypes.byref(t)))
 
     def get_tuning(self, refset_id: int) -> tuple[int, int]:

@@ -75,7 +75,11 @@ def test_full_size_sampled_parity_and_properties(workload):
     # sampled particles against the oracle
     rng = np.random.default_rng(9)
     idx = {0, 1, N - 2, N - 1}
-    for b in (2325, 2326, 4651, 4652, 50000):      # around chunk boundaries of the default workspace
+    # around chunk boundaries of the default workspace (32 GiB, half of it for
+    # the particle operand of 128 slots x 4 ceil(R/4) rings x 16 floats per 8 rows)
+    R4 = (w["r_max"] - w["r_min"] + 4) // 4
+    chunk = (32 << 30) // 2 // ((2 * T + 1) ** 2 * 128 * R4 * 64 * 4 // 8)
+    for b in (chunk, 2 * chunk, 50000):
         idx.update({b - 1, b})
     idx.update(int(i) for i in rng.integers(0, N, 6))
     idx = np.array(sorted(idx))
