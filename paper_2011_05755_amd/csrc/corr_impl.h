@@ -255,44 +255,48 @@ struct Fp32Contract {
 
 // Contraction with 16-bit operands; NS = ceil(MAXR / 8) steps of 8 rings
 // per lane group, R4 <= MAXR (EXACT: every work item has ceil(R4 / 8) == NS).
-// RES: the particle operand is converted once per row tile (scaled for
-// FP16) and kept packed in registers, two values per dword; otherwise it is
-// re-read and converted per reference tile, one slot ahead.
+// The particle operand arrives rounded to the contraction's type (FP16
+// already scaled per particle) in the 16-bit ring-major layout.  RES: it is
+// read once per row tile and kept packed in registers, two values per
+// dword; otherwise it is re-read per reference tile, one slot ahead.
 template <int PREC, int NW, int MAXR, bool EXACT, bool RES>
 struct Half16Contract {
   static constexpr int SPW = kSlots / NW;
   static constexpr int NS = (MAXR + 7) / 8;
   typedef typename Op16<PREC>::T V;
   u32x4 areg[RES ? SPW : 1][NS];
-  float scale_ = 1.f;
   float e[4];  // high-slot energy of the lane's entries (store_block)
 
-  __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, float (&v)[8 * NS], bool nt) {
-    const float* ap = a_lane<kRingMajor>(a, tile, slot, ln);
+  // The lane's elements t (rings (ln/16) R4 + t) of slot `slot`, packed two
+  // per dword.  Loads are never conditional: the index is clamped into the
+  // slot's block and elements t >= R4 and padding rings >= R are cleared by
+  // an AND with a mask the optimiser cannot see through.
+  __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, u32x4 (&dst)[NS], bool nt) {
+    const int R4 = a.R4;
+    const uint16_t* ap = reinterpret_cast<const uint16_t*>(a.A) +
+                         ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + slot) * 16 + (ln & 15);
+    uint32_t v[8 * NS];
 #pragma unroll
-    for (int t = 0; t < 8 * NS; ++t) v[t] = t < MAXR ? a_elem<kRingMajor>(a, ap, ln, t, nt) : 0.f;
-  }
-  __device__ __forceinline__ void pack(const float (&v)[8 * NS], u32x4 (&dst)[NS]) const {
+    for (int t = 0; t < 8 * NS; ++t) {
+      if (t < MAXR) {
+        const int tt = t < R4 ? t : R4 - 1;
+        const uint32_t x = nt ? (uint32_t)__builtin_nontemporal_load(ap + tt * kSlots * 16)
+                              : (uint32_t)ap[tt * kSlots * 16];
+        uint32_t keep = (t < R4 && (ln >> 4) * R4 + t < a.R) ? 0xffffu : 0u;
+        asm("" : "+v"(keep));
+        v[t] = x & keep;
+      } else {
+        v[t] = 0u;
+      }
+    }
 #pragma unroll
-    for (int d = 0; d < 4 * NS; ++d)
-      dst[d / 4][d % 4] = (uint32_t)Op16<PREC>::bits(v[2 * d] * scale_) |
-                          ((uint32_t)Op16<PREC>::bits(v[2 * d + 1] * scale_) << 16);
+    for (int d = 0; d < 4 * NS; ++d) dst[d / 4][d % 4] = v[2 * d] | (v[2 * d + 1] << 16);
   }
 
-  __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln, float scale) {
-    scale_ = scale;
+  __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
-      // issue the loads of several slots before converting any of them, so
-      // the memory latency is paid a few times per workgroup instead of per slot
-      constexpr int kBatch = NS == 1 ? 8 : 4;
 #pragma unroll
-      for (int i0 = 0; i0 < SPW; i0 += kBatch) {
-        float v[kBatch][8 * NS];
-#pragma unroll
-        for (int bb = 0; bb < kBatch; ++bb) fetch(a, tile, w + NW * (i0 + bb), ln, v[bb], true);
-#pragma unroll
-        for (int bb = 0; bb < kBatch; ++bb) pack(v[bb], areg[i0 + bb]);
-      }
+      for (int i = 0; i < SPW; ++i) fetch(a, tile, w + NW * i, ln, areg[i], true);
     }
   }
 
@@ -328,22 +332,19 @@ struct Half16Contract {
     } else {
       // explicit double buffer so that the slot loop need not be unrolled
       uint4 b0[NS], b1[NS];
-      float r0[8 * NS], r1[8 * NS];
-      u32x4 x[NS];
+      u32x4 x0[NS], x1[NS];
       loadb(0, b0);
-      fetch(a, tile, w, ln, r0, false);
+      fetch(a, tile, w, ln, x0, false);
 #pragma unroll 1
       for (int i = 0; i < SPW; i += 2) {
         loadb(i + 1, b1);
-        fetch(a, tile, w + NW * (i + 1), ln, r1, false);
-        pack(r0, x);
-        add_energy(e, chain(x, b0, w + NW * i), i >= kLowSlots / NW ? 1.f : 0.f);
+        fetch(a, tile, w + NW * (i + 1), ln, x1, false);
+        add_energy(e, chain(x0, b0, w + NW * i), i >= kLowSlots / NW ? 1.f : 0.f);
         if (i + 2 < SPW) {
           loadb(i + 2, b0);
-          fetch(a, tile, w + NW * (i + 2), ln, r0, false);
+          fetch(a, tile, w + NW * (i + 2), ln, x0, false);
         }
-        pack(r1, x);
-        add_energy(e, chain(x, b1, w + NW * (i + 1)), i + 1 >= kLowSlots / NW ? 1.f : 0.f);
+        add_energy(e, chain(x1, b1, w + NW * (i + 1)), i + 1 >= kLowSlots / NW ? 1.f : 0.f);
       }
     }
   }
@@ -427,9 +428,7 @@ __device__ __forceinline__ float part_thr(float best, float margin) {
 // Power-of-two FP16 scale of chunk row r: |a +- b| <= 2 * 256 * max|pixel|
 // of the row's particle is mapped below 2^14.
 __device__ __forceinline__ float fp16_scale(const CorrArgs& a, int r) {
-  if (r >= a.rows) return 1.f;
-  const float m = fmaxf(a.maxabs[r / a.S] * 512.f, 1e-30f);
-  return ldexpf(1.f, 14 - (int)ceilf(log2f(m)));
+  return r >= a.rows ? 1.f : fp16_operand_scale(a.maxabs[r / a.S]);
 }
 
 // What a tile computes: the per-row arg-max, the full CC table (debug), or
@@ -472,10 +471,9 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     sm.ppart[tid] = part;
     sm.pt[tid] = (part >= 0 && part == *sm.carry_p) ? *sm.carry_v : -INFINITY;
   }
-  // FP16: the lane's operand row (ln & 7) is scaled by a power of two of its
-  // particle (exact, so results do not depend on how particles are grouped)
-  if constexpr (PREC == kFP32) con.load_a(a, tile, w, ln);
-  else con.load_a(a, tile, w, ln, PREC == kFP16 ? fp16_scale(a, tile * kRowTile + (ln & 7)) : 1.f);
+  // (FP16: each particle's operand rows come scaled by a power of two of its
+  // own, exact, so results do not depend on how particles are grouped)
+  con.load_a(a, tile, w, ln);
   int* list = sm.list + w * 64;
   // Pruning (not in table mode, and not with 4 waves, whose registers are
   // full with the resident operand) stops for the rest of the row tile when a

@@ -147,6 +147,10 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       // 4), slot stride ss: a per-lane part computed once per item and a
       // uniform offset
       const bool slot_major = a.a_layout == kSlotMajor, perm = a.a_layout == kRingPerm;
+      // 16-bit operand: each value rounded once, as the contraction's matrix
+      // cores take it (FP16 scaled by the particle's power of two)
+      const bool half = a.a_layout == kRingMajor16;
+      const float hscale = (half && a.prec == kFP16) ? fp16_operand_scale(a.maxabs[n]) : 1.f;
       const int ss = slot_major ? a.R4 * 64 : 16;
       float* dst = a.out + (slot_major ? (size_t)tile * kSlots * a.R4 * 64 + ring * 16
                                        : ((size_t)tile * 4 * a.R4 + ring) * kSlots * 16);
@@ -190,6 +194,26 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
           }
           const int sl = it * 16 + (lnx >> 2);
           const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
+          if (half) {
+            // the same position in a run of 2-byte elements
+            uint16_t* o16 = reinterpret_cast<uint16_t*>(a.out) + ((size_t)(tile * 4 * a.R4 + ring) * kSlots +
+                                                                  64 * h + sl) * 16 + part * 4;
+            const float vv[4] = {val.x * hscale, val.y * hscale, val.z * hscale, val.w * hscale};
+            uint16_t u[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              u[q] = a.prec == kFP16 ? __builtin_bit_cast(uint16_t, (_Float16)vv[q])
+                                     : __builtin_bit_cast(uint16_t, (__bf16)vv[q]);
+            if (full) {
+              *reinterpret_cast<uint2*>(o16) = make_uint2((uint32_t)u[0] | ((uint32_t)u[1] << 16),
+                                                          (uint32_t)u[2] | ((uint32_t)u[3] << 16));
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                if (r0 + q >= first && r0 + q < last) o16[q] = u[q];
+            }
+            continue;
+          }
           float* o = lane_dst + (size_t)(64 * h + 16 * it) * ss;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;

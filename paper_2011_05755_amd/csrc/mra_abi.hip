@@ -264,7 +264,9 @@ void check_result(const mra_result* r) {
 }
 
 // bytes of the correlation operand A per particle row (one eighth of a tile)
-size_t a_bytes_per_row(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * sizeof(float) / kRowTile; }
+// the operand's element size: 16-bit for the 16-bit contractions
+size_t a_elem(const Refset& rs) { return a_elem_bytes(a_layout_for(rs.g.precision, rs.variant)); }
+size_t a_bytes_per_row(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * a_elem(rs) / kRowTile; }
 
 int64_t chunk_particles(mra_ctx* c, const Refset& rs, const Plan& p) {
   if (rs.chunk > 0) return rs.chunk;
@@ -283,7 +285,7 @@ struct ChunkBufs {
   int32_t* win = nullptr;   // cc2: [nc] chunk-local winner copy
 };
 
-size_t tile_bytes_of(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * sizeof(float); }
+size_t tile_bytes_of(const Refset& rs) { return (size_t)kSlots * rs.R4 * 64 * a_elem(rs); }
 
 // Lays the buffers of an nc-particle chunk out from `base` (256-byte
 // aligned pieces); returns the bytes used.  base = nullptr only measures.
@@ -374,7 +376,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   int* ridx = bufs.ridx;
   // rows past the chunk in its last tile are read as zeros
   if (rows % kRowTile)
-    hip_check(c, launch_fill_zero(A + (size_t)(tiles - 1) * tile_bytes / sizeof(float), tile_bytes, st), "fill");
+    hip_check(c, launch_fill_zero((char*)A + (size_t)(tiles - 1) * tile_bytes, tile_bytes, st), "fill");
   const float* src = parts + (size_t)n0 * L * L;
 
   float* maxabs = nullptr;
@@ -391,6 +393,8 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   pa.r_min = rs.g.r_min;
   // the CC table is written by the form launch_corr picks for it
   pa.a_layout = a_layout_for(rs.g.precision, table ? (rs.g.precision == kFP32 ? 2 : 0) : rs.variant);
+  pa.prec = rs.g.precision;
+  pa.maxabs = maxabs;
   pa.cs64 = c->cs64;
   pa.out = A;
   timed(c, "polar", [&] { hip_check(c, launch_polar(0, pa, st), "polar"); });
@@ -522,7 +526,7 @@ struct Piece {
   Plan p;
   int64_t n0;
   int nc;
-  size_t a_off;  // first float of the piece in the wave's A buffer
+  size_t a_off;  // first byte of the piece in the wave's A buffer
   size_t row0;   // first row in the wave's row-result buffers
 };
 
@@ -536,16 +540,16 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
   }
   const Refset& rs0 = *w[0].rs;
   const int prec = rs0.g.precision, variant = rs0.variant;
-  size_t a_floats = 0, rows = 0, part_total = 0;
+  size_t a_bytes = 0, rows = 0, part_total = 0;
   for (Piece& pc : w) {
     part_total += pc.nc;
-    pc.a_off = a_floats;
+    pc.a_off = a_bytes;
     pc.row0 = rows;
     const size_t r = (size_t)pc.nc * pc.p.S;
-    a_floats += (r + kRowTile - 1) / kRowTile * (size_t)kSlots * pc.rs->R4 * 64;
+    a_bytes += (r + kRowTile - 1) / kRowTile * tile_bytes_of(*pc.rs);
     rows += r;
   }
-  float* A = (float*)ws_get(c, "A", a_floats * sizeof(float));
+  char* A = (char*)ws_get(c, "A", a_bytes);
   float* rcc = (float*)ws_get(c, "row_cc", rows * sizeof(float));
   int* ridx = (int*)ws_get(c, "row_idx", rows * sizeof(int));
   float* maxabs = prec == kFP16 ? (float*)ws_get(c, "maxabs", (size_t)part_total * sizeof(float)) : nullptr;
@@ -563,11 +567,11 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     const int L = rs.g.L;
     const int prow = pc.nc * pc.p.S;
     const int ptiles = (prow + kRowTile - 1) / kRowTile;
-    const size_t tile_floats = (size_t)kSlots * rs.R4 * 64;
-    float* Ap = A + pc.a_off;
+    const size_t tile_bytes = tile_bytes_of(rs);
+    float* Ap = (float*)(A + pc.a_off);
     const float* src = sk.parts + (size_t)pc.n0 * L * L;
     if (prow % kRowTile)
-      hip_check(c, launch_fill_zero(Ap + (size_t)(ptiles - 1) * tile_floats, tile_floats * sizeof(float), st), "fill");
+      hip_check(c, launch_fill_zero((char*)Ap + (size_t)(ptiles - 1) * tile_bytes, tile_bytes, st), "fill");
     float* mx = nullptr;
     if (maxabs) {
       mx = maxabs + part;
@@ -578,6 +582,8 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     pa.L = L; pa.R = rs.R; pa.R4 = rs.R4; pa.T = pc.p.T; pa.S1 = pc.p.S1; pa.S = pc.p.S;
     pa.Lp = pc.p.Lp; pa.pad = pc.p.pad; pa.cx = pc.p.cx; pa.r_min = rs.g.r_min; pa.cs64 = c->cs64; pa.out = Ap;
     pa.a_layout = a_layout_for(prec, variant);
+    pa.prec = prec;
+    pa.maxabs = mx;
     pb.start[i] = part;
 
     CorrArgs& ca = cb.piece[i];

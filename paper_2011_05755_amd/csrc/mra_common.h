@@ -38,11 +38,23 @@ enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 //               operand resident)
 //   kSlotMajor  [slot][ring < 4*R4][16]: each slot's rings contiguous (FP32
 //               4-wave and streamed contractions, which re-read the operand)
-enum ALayout { kRingMajor = 0, kRingPerm = 1, kSlotMajor = 2 };
+//   kRingMajor16  kRingMajor with 16-bit elements, rounded once by the
+//               resampler in the contraction's type (BF16, or FP16 scaled by
+//               a power of two per particle): the 16-bit forms
+enum ALayout { kRingMajor = 0, kRingPerm = 1, kSlotMajor = 2, kRingMajor16 = 3 };
 __host__ __device__ constexpr int slot_pos(int s) { return (s & 7) * 16 + (s >> 3); }
 // The layout a correlation launch reads (and the resampler must write).
 __host__ __device__ constexpr int a_layout_for(int prec, int variant) {
-  return prec != kFP32 ? kRingMajor : (variant == 0 ? kRingPerm : kSlotMajor);
+  return prec != kFP32 ? kRingMajor16 : (variant == 0 ? kRingPerm : kSlotMajor);
+}
+// bytes per operand element of a layout
+__host__ __device__ constexpr int a_elem_bytes(int layout) { return layout == kRingMajor16 ? 2 : 4; }
+
+// Power-of-two FP16 scale of a particle's operand: |a +- b| <= 2 * 256 *
+// max|pixel| is mapped below 2^14.
+__device__ __forceinline__ float fp16_operand_scale(float maxabs) {
+  const float m = fmaxf(maxabs * 512.f, 1e-30f);
+  return ldexpf(1.f, 14 - (int)ceilf(log2f(m)));
 }
 
 // Entry of the particle sampling stencil for ring r and angle j (FP64
@@ -67,13 +79,15 @@ struct PolarArgs {
   int Lp, pad, cx;     // LDS image side (with zero border), border width, centre
   int r_min;           // radius of ring 0
   int a_layout;        // mode 0: ALayout of the operand
+  int prec;            // kRingMajor16: kBF16 or kFP16
+  const float* maxabs; // kFP16: max |pixel| of each particle of the chunk (operand scale)
   const double2* cs64; // (cos, sin)(2 pi j / 256)
-  float* out;
+  float* out;          // (mode 0, kRingMajor16: 16-bit elements)
 };
 
 // Fused contraction + inverse FFT over angle + arg-max.
 struct CorrArgs {
-  const float* A;        // [row tiles][...] in layout a_layout (ALayout)
+  const float* A;        // [row tiles][...] in layout a_layout (ALayout; 16-bit elements for kRingMajor16)
   int a_layout;
   int n_row_tiles;
   int rows;              // valid rows in the chunk (n * S)
