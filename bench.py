@@ -11,16 +11,23 @@ before timing; particles are resident in HBM when the timed region starts.
 Prints one JSON line.  `value` is the FP32 form's aligned particles/s; the
 BF16-matrix-core form (FP32 re-score of the winner) is reported beside it.
 `roofline` covers the dominant kernel (the fused correlation kernel), timed
-with HIP events on the library's stream; `cpu_baseline` times the FP64
-oracle on a sample of the same stack.
+with HIP events on the library's stream; its `traffic` (HBM bytes per
+launch) comes from the counter summary under profiles/ when that summary was
+taken on the current kernel sources, else null.  `serving` runs the
+continuous-batching server on a bounded trace (BF16, 8 resident refsets of
+the uneven-stack distribution, Poisson arrivals at 20/s and at a rate one
+GPU sustains) and reports p50/p99 latency and particles/s.  `cpu_baseline`
+times the FP64 oracle on a sample of the same stack.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
+import re
 import statistics
 import sys
 import time
@@ -39,11 +46,40 @@ FP32_VECTOR_PEAK = 157.3   # TFLOP/s, MI355X FP32 vector (published; counts pack
 # x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_VALU_PEAK = 78.6
 HBM_PEAK = 8000.0          # GB/s
-# HBM bytes per launch of the FP32 correlation kernel on this workload, from
-# FETCH_SIZE (x2.000) and WRITE_SIZE (x1.000) counters calibrated on a 1 GiB
-# copy (profiles/mra_c1_hbm_traffic.md).  Set to None when the kernel changes
-# until the counters are taken again.
-CORR_FP32_TRAFFIC_BYTES = 4.571e9
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "mra_c1_hbm_traffic.md")
+CSRC = os.path.join(ROOT, "paper_2011_05755_amd", "csrc")
+# sources each kernel's code is built from (a change to any of them voids
+# counter figures taken before it)
+KERNEL_SOURCES = {
+    "k_corr": ["corr_impl.h", "k_corr.hip", "k_corr_fp32.hip", "k_corr_bf16.hip", "k_corr_fp16.hip", "mra_common.h",
+               "mra_fft.h"],
+    "k_polar_fft": ["k_polar.hip", "polar_impl.h", "mra_fft.h", "mra_common.h"],
+    "k_avg": ["k_avg.hip", "mra_common.h"],
+}
+
+
+def kernel_sources_sha(kernel: str) -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel: str, form: str, workspace_gib: int):
+    """HBM bytes per launch of `kernel` in `form` from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when the summary is missing, was taken with another chunking, or on
+    other kernel sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            m = re.search(r"<!-- traffic: (\{.*?\}) -->", f.read(), re.S)
+        e = json.loads(m.group(1))[kernel][form]
+    except (OSError, AttributeError, KeyError, ValueError):
+        return None
+    if e.get("sources_sha") != kernel_sources_sha(kernel) or e.get("workspace_gib") != workspace_gib:
+        return None
+    return float(e["bytes_per_launch"])
 
 
 def log(msg):
@@ -62,6 +98,47 @@ def ifft_flops_per_row_ref() -> float:
     return 32 * (128 + 42) + 225 * 6.0
 
 
+def run_serving(args, bench_ctx, dev) -> dict:
+    """Two bounded traces of the serving workload (8 resident BF16 refsets
+    drawn from the uneven-stack distribution; request sizes N ~ U{2k..50k},
+    each a slice of one pre-generated device stack per refset): Poisson 20/s,
+    which offers more than one GPU serves, and a sustainable rate.  Latency
+    is completion minus arrival; the first requests of each trace are not
+    left out (the server starts empty)."""
+    import torch
+    from paper_2011_05755_amd import mra, serve
+    ws = 8 << 30
+    ctx = mra.Context(0, workspace_cap=ws)
+    sets = serve.make_refsets(ctx, 8, seed=5, precision="bf16")
+    out = {}
+    legs = [(args.serve_rate, args.serve_requests), (args.serve_sustained_rate, args.serve_sustained)]
+    for j, (rate, n_req) in enumerate(legs):
+        if n_req <= 0:
+            continue
+        arrivals = serve.make_requests(sets, n_req, rate, seed=5 + j, device=dev, pool=True)
+        torch.cuda.synchronize()
+        srv = serve.Server(serve.AlignExecutor(ctx), hbm_budget=96 << 30, workspace_bytes=ws, step_rows=1 << 18)
+        log(f"serving: {n_req} requests at Poisson {rate}/s")
+        stats = serve.run_trace(srv, arrivals)
+        torch.cuda.synchronize()
+        offered = sum(r.N for _, r in arrivals) / max(arrivals[-1][0], 1e-9)
+        out[f"poisson_{rate:g}_per_s"] = dict(
+            requests=stats["requests"], failed=stats["failed_requests"], particles=stats["particles"],
+            p50_latency_s=round(stats["p50_s"], 4), p99_latency_s=round(stats["p99_s"], 4),
+            particles_per_s=round(stats["particles_per_s"], 1), offered_particles_per_s=round(offered, 1),
+            makespan_s=round(stats["makespan_s"], 3), max_waiting=stats["max_waiting"])
+        log(f"serving {rate}/s: p50 {stats['p50_s']:.3f} s, p99 {stats['p99_s']:.3f} s, "
+            f"{stats['particles_per_s']:.4g} particles/s (offered {offered:.4g})")
+        del arrivals, srv
+    ctx.close()
+    del sets
+    torch.cuda.empty_cache()
+    out["workload"] = ("8 resident refsets (uneven-stack distribution: L in {64,76,96,128}, K 20..400, shifts "
+                       "+-2..+-5, rings 1..L/2-2), BF16 with FP32 re-ranking, request N ~ U{2000..50000} "
+                       "(slices of one device-resident stack per refset), 96 GiB admission budget")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +151,12 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reads and writes MIB MiB), "
                          "a reference for hardware traffic counters")
+    ap.add_argument("--workspace-gib", type=int, default=32, help="library workspace cap (chunk size)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the 20/s serving leg (0: no serving legs)")
+    ap.add_argument("--serve-sustained", type=int, default=16, help="requests of the sustainable-rate leg")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-sustained-rate", type=float, default=2.5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -103,7 +186,7 @@ def main() -> int:
     parts, truth = synth.make_particles(blobs, N, T, w["snr"], seed=(w["seed"], 1), device=dev)
     torch.cuda.synchronize()
 
-    ctx = mra.Context(0)
+    ctx = mra.Context(0, workspace_cap=args.workspace_gib << 30)
     forms = [f for f in args.forms.split(",") if f]
     results = {}
     for i, form in enumerate(forms):
@@ -174,7 +257,7 @@ def main() -> int:
     roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
                     frac=round(achieved / peak, 4),
                     frac_padded=round(padded / (corr_ms / 1000.0) / 1e12 / peak, 4),
-                    traffic=CORR_FP32_TRAFFIC_BYTES if head == "fp32" else None,
+                    traffic=traffic_from_profile("k_corr", head, args.workspace_gib),
                     traffic_unit="bytes per launch (HBM, counter-measured)",
                     kernel="k_corr", launches_per_step=corr_n // args.steps,
                     avg_launch_ms=round(corr_ms / corr_n, 4),
@@ -186,6 +269,9 @@ def main() -> int:
             continue
         r = results[form]
         cms, cn = r["kern"]["corr"]
+        pms, _ = r["kern"]["polar"]
+        # 16-bit forms: ring spectra written as 2-byte values
+        pol16 = (N * L * L * 4 + N * S * 512 * R) * args.steps / (pms / 1000.0) / 1e9
         alu = ifft_flops_per_row_ref() * N * S * K * args.steps / (cms / 1000.0) / 1e12
         mf = corr_flops_per_row_ref(R) * N * S * K * args.steps / (cms / 1000.0) / 1e12
         extra[form] = dict(value=round(r["value"], 1), ms_per_step=round(r["ms"], 3),
@@ -193,7 +279,9 @@ def main() -> int:
                            speedup_vs_fp32=round(results[head]["ms"] / r["ms"], 3) if head == "fp32" else None,
                            corr_avg_launch_ms=round(cms / cn, 4),
                            corr_matrix_tflops=round(mf, 2), corr_matrix_frac=round(mf / BF16_MATRIX_PEAK, 4),
-                           corr_ifft_valu_tflops=round(alu, 2), corr_ifft_valu_frac=round(alu / FP32_VALU_PEAK, 4))
+                           corr_ifft_valu_tflops=round(alu, 2), corr_ifft_valu_frac=round(alu / FP32_VALU_PEAK, 4),
+                           corr_traffic_bytes_per_launch=traffic_from_profile("k_corr", form, args.workspace_gib),
+                           polar_hbm_gbps=round(pol16, 1), polar_hbm_frac=round(pol16 / HBM_PEAK, 4))
 
     kernels = {form: {k: round(v[0] / args.steps, 3) for k, v in r["kern"].items() if v[1]}
                for form, r in results.items()}
@@ -215,6 +303,11 @@ def main() -> int:
                             frac=round(ifft / FP32_VALU_PEAK, 4), flops_per_row_ref=ifft_flops_per_row_ref(),
                             note="inverse FFT share of the fused correlation kernel, same launches"),
     }
+
+    # ---- serving: continuous batching on bounded Poisson traces (BF16) ----
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args, ctx, dev)
 
     # ---- CPU baseline: the FP64 oracle on a sample of the same stack ----
     cpu = None
@@ -287,6 +380,7 @@ def main() -> int:
         "rooflines_other_kernels": rooflines,
         "kernels_ms_per_step": kernels,
         "with_h2d": h2d,
+        "serving": serving,
     }
     line.update(extra)
     if parity is not None:
