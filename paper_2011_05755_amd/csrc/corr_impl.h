@@ -37,6 +37,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kMaxBatch = kMaxBatchPieces;
 
@@ -253,25 +254,39 @@ struct Fp32Contract {
   }
 };
 
-// Contraction with 16-bit operands; NS = ceil(MAXR / 8) steps of 8 rings
-// per lane group, R4 <= MAXR (EXACT: every work item has ceil(R4 / 8) == NS).
-// The particle operand arrives rounded to the contraction's type (FP16
-// already scaled per particle) in the 16-bit ring-major layout.  RES: it is
-// read once per row tile and kept packed in registers, two values per
-// dword; otherwise it is re-read per reference tile, one slot ahead.
+// Contraction with 16-bit operands; NS = ceil(MAXR / 8) <= 2 steps of 8
+// rings per lane group, R4 <= MAXR (EXACT: every work item has
+// ceil(R4 / 8) == NS).  With MAXR = 12 the second step holds at most 4 rings
+// per lane group (NARROW): the resident particle operand keeps 2 dwords of it
+// per slot instead of 4.  The particle operand
+// arrives rounded to the contraction's type (FP16 already scaled per
+// particle) in the 16-bit ring-major layout.  RES: it is read once per row
+// tile and kept packed in registers, two values per dword; otherwise it is
+// re-read per reference tile, one slot ahead.  The reference operand's last
+// step is stored as wide as its rings need (b16_tail_width) and read with
+// dword loads of that width.
 template <int PREC, int NW, int MAXR, bool EXACT, bool RES>
 struct Half16Contract {
   static constexpr int SPW = kSlots / NW;
   static constexpr int NS = (MAXR + 7) / 8;
+  static_assert(NS <= 2, "at most two steps of 8 rings per lane group");
+  static constexpr bool NARROW = NS == 2 && MAXR - 8 <= 4;
+  static constexpr int NF = NARROW ? 1 : NS;  // steps held 8 wide
   typedef typename Op16<PREC>::T V;
-  u32x4 areg[RES ? SPW : 1][NS];
+  // one slot's operand of the lane: the steps held 8 wide, then (NARROW) the
+  // last step's 4 elements
+  struct Frag {
+    u32x4 f[NF];
+    u32x2 t;
+  };
+  Frag areg[RES ? SPW : 1];
   float e[4];  // high-slot energy of the lane's entries (store_block)
 
   // The lane's elements t (rings (ln/16) R4 + t) of slot `slot`, packed two
   // per dword.  Loads are never conditional: the index is clamped into the
   // slot's block and elements t >= R4 and padding rings >= R are cleared by
   // an AND with a mask the optimiser cannot see through.
-  __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, u32x4 (&dst)[NS], bool nt) {
+  __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, Frag& dst, bool nt) {
     const int R4 = a.R4;
     const uint16_t* ap = reinterpret_cast<const uint16_t*>(a.A) +
                          ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + slot) * 16 + (ln & 15);
@@ -290,7 +305,11 @@ struct Half16Contract {
       }
     }
 #pragma unroll
-    for (int d = 0; d < 4 * NS; ++d) dst[d / 4][d % 4] = v[2 * d] | (v[2 * d + 1] << 16);
+    for (int d = 0; d < 4 * NF; ++d) dst.f[d / 4][d % 4] = v[2 * d] | (v[2 * d + 1] << 16);
+    if constexpr (NARROW) {
+      dst.t[0] = v[8] | (v[9] << 16);
+      dst.t[1] = v[10] | (v[11] << 16);
+    }
   }
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
@@ -301,24 +320,47 @@ struct Half16Contract {
   }
 
   __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
-    const uint4* B = reinterpret_cast<const uint4*>(a.B16);
     const int ns = EXACT ? NS : a.NS;
+    const int bt = a.BT;                          // last step: bt elements per lane
+    const int se = (ns - 1) * 512 + 64 * bt;      // elements per slot block
+    const int h = bt / 2;                         // dwords per lane in the last step
+    // Last-step dword j of the lane is read at index min(j, h - 1): a dword
+    // j >= h repeats stored values, which meet the particle operand's
+    // elements t >= R4, all zero, so it adds exact zeros (every stored value
+    // is finite).  With ns == 1 the last-step address is step 0's, read and
+    // unused.
     e[0] = e[1] = e[2] = e[3] = 0.f;
-    auto loadb = [&](int i, uint4 (&dst)[NS]) {
-      const uint4* bp = B + ((size_t)(kt * kSlots + w + NW * i) * ns) * 64 + ln;
+    auto loadb = [&](int i, Frag& dst) {
+      const uint16_t* bp = a.B16 + (size_t)(kt * kSlots + w + NW * i) * se;
+      dst.f[0] = *reinterpret_cast<const u32x4*>(bp + ln * 8);  // step 0 is always 8 wide
+      if constexpr (NS == 2) {
+        const uint32_t* tp = reinterpret_cast<const uint32_t*>(bp + (ns - 1) * 512 + ln * bt);
+        if constexpr (NARROW) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) dst[s] = bp[(s < ns ? s : ns - 1) * 64];  // unconditional
+          for (int j = 0; j < 2; ++j) dst.t[j] = tp[j < h ? j : h - 1];
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dst.f[1][j] = tp[j < h ? j : h - 1];
+        }
+      }
     };
-    auto chain = [&](const u32x4 (&x)[NS], const uint4 (&y)[NS], int slot) {
+    auto chain = [&](const Frag& x, const Frag& y, int slot) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < NS; ++s)
-        if (s < ns) acc = Op16<PREC>::mfma(__builtin_bit_cast(V, x[s]), __builtin_bit_cast(V, y[s]), acc);
+      for (int s = 0; s < NF; ++s)
+        if (s < ns) acc = Op16<PREC>::mfma(__builtin_bit_cast(V, x.f[s]), __builtin_bit_cast(V, y.f[s]), acc);
+      if constexpr (NARROW) {
+        // the last step is a K = 32 product with elements 4..7 zero: a K = 16
+        // product accumulated straight onto the K = 32 one's result gave
+        // wrong sums on gfx950 when the two issued back to back
+        const u32x4 xa = {x.t[0], x.t[1], 0u, 0u}, yb = {y.t[0], y.t[1], 0u, 0u};
+        if (ns == NS) acc = Op16<PREC>::mfma(__builtin_bit_cast(V, xa), __builtin_bit_cast(V, yb), acc);
+      }
       store_block(st, slot, ln, acc);
       return acc;
     };
     if constexpr (RES) {
-      uint4 b[2][NS];
+      Frag b[2];
       loadb(0, b[0]);
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
@@ -331,8 +373,7 @@ struct Half16Contract {
       }
     } else {
       // explicit double buffer so that the slot loop need not be unrolled
-      uint4 b0[NS], b1[NS];
-      u32x4 x0[NS], x1[NS];
+      Frag b0, b1, x0, x1;
       loadb(0, b0);
       fetch(a, tile, w, ln, x0, false);
 #pragma unroll 1

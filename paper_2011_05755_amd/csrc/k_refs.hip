@@ -5,7 +5,8 @@
 //   Q_k[r][f]  per-ring DFT (direct sum), times w_r / (nu_k * 256),
 // then packed into the operand layouts of the correlation kernel:
 //   FP32  [ref tile][slot][t < R4][64], lane = g*16 + q*8 + ref%8, ring = g*R4 + t
-//   16-bit [ref tile][slot][s < NS][64][8], ring = g*R4 + 8 s + e
+//   16-bit [ref tile][slot][s < NS - 1][64][8], ring = g*R4 + 8 s + e, then
+//          the last step [64][BT] (BT = 2, 4 or 8: as wide as its rings need)
 // with q = 0 -> c - d and q = 1 -> c + d for c + id = Q_f (slot f = 1..127)
 // and c = Q_0, d = Q_128 in slot 0; with one reference also
 //   single [ring][slot] (c - d, c + d) for the fused single-reference kernel.
@@ -118,13 +119,22 @@ __global__ void k_ref_pack32(RefArgs a) {
 }
 
 __global__ void k_ref_pack16(RefArgs a) {
-  const int64_t total = (int64_t)a.n_ref_tiles * kSlots * a.NS * 64 * 8;
+  const int se = b16_slot_elems(a.R4), bt = b16_tail_width(a.R4);
+  const int64_t total = (int64_t)a.n_ref_tiles * kSlots * se;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= total) return;
-  const int e = i % 8, lane = (i / 8) % 64;
-  const int s = (i / 512) % a.NS;
-  const int slot = (i / (512 * (int64_t)a.NS)) % kSlots, kt = i / (512 * (int64_t)a.NS * kSlots);
-  const double v = packed_value(a, kt, slot, lane, 8 * s + e) * a.b_scale;
+  const int off = i % se;
+  const int slot = (i / se) % kSlots, kt = i / ((int64_t)se * kSlots);
+  const int full = (a.NS - 1) * 512;  // elements of the steps stored 8 wide
+  int lane, t;
+  if (off < full) {
+    lane = (off / 8) % 64;
+    t = 8 * (off / 512) + off % 8;
+  } else {
+    lane = (off - full) / bt;
+    t = 8 * (a.NS - 1) + (off - full) % bt;
+  }
+  const double v = packed_value(a, kt, slot, lane, t) * a.b_scale;
   if (a.prec == kBF16) {
     __bf16 h = (__bf16)(float)v;
     a.B16[i] = __builtin_bit_cast(uint16_t, h);
@@ -171,7 +181,7 @@ hipError_t launch_ref_stage2(const RefArgs& a, hipStream_t st) {
     const int64_t n = (int64_t)a.n_ref_tiles * kSlots * a.R4 * 64;
     hipLaunchKernelGGL(k_ref_pack32, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
   } else {
-    const int64_t n = (int64_t)a.n_ref_tiles * kSlots * a.NS * 64 * 8;
+    const int64_t n = (int64_t)a.n_ref_tiles * kSlots * b16_slot_elems(a.R4);
     hipLaunchKernelGGL(k_ref_pack16, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
   }
   return hipGetLastError();

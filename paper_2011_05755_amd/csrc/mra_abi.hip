@@ -406,7 +406,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.rows = rows;
   ca.B32 = rs.B32;
   ca.B16 = rs.B16;
-  ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = p.S; ca.M = p.M;
+  ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.BT = b16_tail_width(rs.R4); ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = p.S; ca.M = p.M;
   ca.maxabs = maxabs;
   ca.b_scale = rs.b_scale;
   ca.cs32 = c->cs32;
@@ -589,7 +589,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     CorrArgs& ca = cb.piece[i];
     ca.A = Ap; ca.a_layout = pa.a_layout; ca.n_row_tiles = ptiles; ca.rows = prow;
     ca.B32 = rs.B32; ca.B16 = rs.B16;
-    ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = pc.p.S; ca.M = pc.p.M;
+    ca.R = rs.R; ca.R4 = rs.R4; ca.NS = rs.NS; ca.BT = b16_tail_width(rs.R4); ca.n_ref_tiles = rs.n_kt; ca.K = rs.K; ca.S = pc.p.S; ca.M = pc.p.M;
     ca.maxabs = mx; ca.b_scale = rs.b_scale; ca.cs32 = c->cs32;
     ca.row_cc = rcc + pc.row0; ca.row_idx = ridx + pc.row0; ca.table = nullptr; ca.prune = rs.prune;
     ca.tiles_per_run = rs.run_tiles > 0 ? rs.run_tiles : corr_tiles_per_run(ptiles, c->n_cu);
@@ -747,7 +747,7 @@ void load_refs_impl(mra_ctx* c, int32_t id, const float* refs, int32_t K, const 
     if (g->precision == kFP32)
       rs.B32 = (float*)alloc(c, (size_t)rs.n_kt * kSlots * rs.R4 * 64 * sizeof(float), "B32");
     else
-      rs.B16 = (uint16_t*)alloc(c, (size_t)rs.n_kt * kSlots * rs.NS * 64 * 8 * sizeof(uint16_t), "B16");
+      rs.B16 = (uint16_t*)alloc(c, (size_t)rs.n_kt * kSlots * b16_slot_elems(rs.R4) * sizeof(uint16_t), "B16");
     ra.B32 = rs.B32;
     ra.B16 = rs.B16;
     if (K == 1) rs.G1 = (float2*)alloc(c, (size_t)rs.R * kSlots * sizeof(float2), "G1");

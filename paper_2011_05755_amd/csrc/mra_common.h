@@ -50,6 +50,17 @@ __host__ __device__ constexpr int a_layout_for(int prec, int variant) {
 // bytes per operand element of a layout
 __host__ __device__ constexpr int a_elem_bytes(int layout) { return layout == kRingMajor16 ? 2 : 4; }
 
+// 16-bit reference operand of one (reference tile, slot): NS = ceil(R4 / 8)
+// steps of 8 rings per lane group; with NS >= 2 the last step is stored only
+// as wide as the rings it holds (2, 4 or 8 elements per lane): the
+// contraction reads that many, and the elements it pads with meet zeros of
+// the particle operand.
+__host__ __device__ constexpr int b16_tail_width(int R4) {
+  return R4 <= 8 ? 8 : (R4 - 8 * ((R4 - 1) / 8) <= 2 ? 2 : (R4 - 8 * ((R4 - 1) / 8) <= 4 ? 4 : 8));
+}
+// 16-bit elements per (reference tile, slot) block
+__host__ __device__ constexpr int b16_slot_elems(int R4) { return (((R4 + 7) / 8 - 1) * 8 + b16_tail_width(R4)) * 64; }
+
 // Power-of-two FP16 scale of a particle's operand: |a +- b| <= 2 * 256 *
 // max|pixel| is mapped below 2^14.
 __device__ __forceinline__ float fp16_operand_scale(float maxabs) {
@@ -92,8 +103,9 @@ struct CorrArgs {
   int n_row_tiles;
   int rows;              // valid rows in the chunk (n * S)
   const float* B32;      // [ref tiles][128][R4][64]
-  const uint16_t* B16;   // [ref tiles][128][NS][64][8]
+  const uint16_t* B16;   // [ref tiles][128][b16_slot_elems(R4)]: NS - 1 steps [64][8], then [64][BT]
   int R, R4, NS, n_ref_tiles, K, S, M;
+  int BT;                // b16_tail_width(R4)
   const float* maxabs;   // FP16: max |pixel| of each particle of the chunk (A scale), else null
   float b_scale;         // FP16: power-of-two scale folded into B16
   const float2* cs32;

@@ -110,14 +110,17 @@ def test_ring_spectra_match_numpy_rfft_of_the_same_samples(ctx):
     assert err < 2e-6, err
 
 
+# rings 1..r_max: R4 = 8, 9, 12, 16 (one step of 8 rings per lane group; two
+# with the 16-bit reference operand's last step 2, 4 or 8 wide)
+@pytest.mark.parametrize("L,r_max", [(64, 30), (76, 35), (96, 46), (128, 62)])
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3), ("fp16", 2e-3)])
-def test_full_cc_table(ctx, precision, tol):
-    log(f"full CC table {precision}")
-    L, K, T, N = 64, 10, 2, 5
+def test_full_cc_table(ctx, precision, tol, L, r_max):
+    log(f"full CC table {precision} L={L} rings 1..{r_max}")
+    K, T, N = 10, 2, 5
     refs, parts, _ = make_case(L, K, T, N, 0.1, 23)
-    ctx.load_refs(4, refs, r_min=1, r_max=30, shift_max=T, precision=precision)
+    ctx.load_refs(4, refs, r_min=1, r_max=r_max, shift_max=T, precision=precision)
     got = ctx.debug_cctable(4, parts).cpu().numpy()
-    want = oracle.cc_table(parts.cpu().numpy(), refs.cpu().numpy(), geom(L, 30, T))
+    want = oracle.cc_table(parts.cpu().numpy(), refs.cpu().numpy(), geom(L, r_max, T))
     for n in range(N):
         scale = np.abs(want[n]).max()
         err = np.abs(got[n] - want[n]).max() / scale
