@@ -396,8 +396,8 @@ struct CorrSmem {
   float* st;                // [128][2][64][2] spectra of the 64 (row, ref) pairs
   float2* stc;
   unsigned long long* key;  // [8] best candidate of each row so far (ordered key, 0 = none)
-  float* pe;                // [2][NW][2][64] high-slot energy per (reference-tile parity, wave, p half, pair)
-  float2* pb;               // [2][NW][64] low-slot bound of each pair (both mirrors), per parity and wave
+  float4* pp;               // [2][NW][64] per (reference-tile parity, wave, pair): low-slot bound of
+                            // both mirrors, high-slot energy of the two p halves
   int* list;                // [NW][64] each wave's list of the pairs that need the inverse FFT
   float* thr;               // [8] each row's best before this reference tile's inverse FFT
   float* pt;                // [8] best over the rows of the row's particle (this tile and carried)
@@ -409,9 +409,8 @@ struct CorrSmem {
     st = smem;
     stc = reinterpret_cast<float2*>(smem);
     key = reinterpret_cast<unsigned long long*>(smem + kSlots * 2 * 64 * 2);
-    pe = reinterpret_cast<float*>(key + 8);
-    pb = reinterpret_cast<float2*>(pe + 2 * NW * 2 * 64);
-    list = reinterpret_cast<int*>(pb + 2 * NW * 64);
+    pp = reinterpret_cast<float4*>(key + 8);
+    list = reinterpret_cast<int*>(pp + 2 * NW * 64);
     thr = reinterpret_cast<float*>(list + NW * 64);
     pt = thr + 8;
     ppart = reinterpret_cast<int*>(pt + 8);
@@ -421,7 +420,7 @@ struct CorrSmem {
   }
   static constexpr size_t bytes() {
     return (size_t)kSlots * 2 * 64 * 2 * sizeof(float) + 8 * sizeof(unsigned long long) +
-           2 * NW * 2 * 64 * sizeof(float) + 2 * NW * 64 * sizeof(float2) + NW * 64 * sizeof(int) +
+           2 * NW * 64 * sizeof(float4) + NW * 64 * sizeof(int) +
            8 * sizeof(float) * 2 + 8 * sizeof(int) + 2 * sizeof(float) + 2 * sizeof(int) + kNphi * sizeof(float2);
   }
 };
@@ -538,7 +537,10 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
       if ((ln & 8) == 0) {
         const int ref = ln & 7, row0 = ((ln >> 4) & 1) * 4, p = ln >> 5;
 #pragma unroll
-        for (int i2 = 0; i2 < 4; ++i2) sm.pe[((par * NW + w) * 2 + p) * 64 + (row0 + i2) * 8 + ref] = e[i2];
+        for (int i2 = 0; i2 < 4; ++i2) {
+          float* q = reinterpret_cast<float*>(&sm.pp[(par * NW + w) * 64 + (row0 + i2) * 8 + ref]);
+          q[2 + p] = e[i2];
+        }
       }
       // exact terms of the wave's own low slots (written by this wave)
       lds_wave_sync();
@@ -559,7 +561,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
           b1 += sqrtf(s2 * s2 + d1 * d1);
         }
       }
-      sm.pb[(par * NW + w) * 64 + P] = make_float2(b0, b1);
+      *reinterpret_cast<float2*>(&sm.pp[(par * NW + w) * 64 + P]) = make_float2(b0, b1);
     }
     __syncthreads();
     // each row's best before this tile's candidates arrive: candidates of this
@@ -574,10 +576,10 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
       float B0 = 0.f, B1 = 0.f, E = 0.f;
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) {
-        const float2 b = sm.pb[(par * NW + w2) * 64 + P];
+        const float4 b = sm.pp[(par * NW + w2) * 64 + P];
         B0 += b.x;
         B1 += b.y;
-        E += sm.pe[((par * NW + w2) * 2) * 64 + P] + sm.pe[((par * NW + w2) * 2 + 1) * 64 + P];
+        E += b.z + b.w;
       }
       const float bound = (a.M == 2 ? fmaxf(B0, B1) : B0) + sqrtf(2.f * (kSlots - kLowSlots) * E);
       const int row_l = P >> 3, ref_l = P & 7;
