@@ -282,24 +282,36 @@ struct Half16Contract {
   Frag areg[RES ? SPW : 1];
   float e[4];  // high-slot energy of the lane's entries (store_block)
 
-  // The lane's elements t (rings (ln/16) R4 + t) of slot `slot`, packed two
-  // per dword.  Loads are never conditional: the index is clamped into the
-  // slot's block and elements t >= R4 and padding rings >= R are cleared by
-  // an AND with a mask the optimiser cannot see through.
+  // Element t (ring (ln/16) R4 + t) of the lane's row for each t < MAXR is
+  // read unconditionally: the index is clamped into the row tile's rings,
+  // and elements t >= R4 and padding rings >= R are cleared by an AND with a
+  // mask the optimiser cannot see through.
+  __device__ __forceinline__ uint32_t keep_mask(const CorrArgs& a, int t, int ln) const {
+    uint32_t keep = (t < a.R4 && (ln >> 4) * a.R4 + t < a.R) ? ~0u : 0u;
+    asm("" : "+v"(keep));
+    return keep;
+  }
+  __device__ __forceinline__ const uint16_t* ring_block(const CorrArgs& a, int tile, int t, int ln) const {
+    const int tt = t < a.R4 ? t : a.R4 - 1;
+    return reinterpret_cast<const uint16_t*>(a.A) + ((size_t)(tile * 4 + (ln >> 4)) * a.R4 + tt) * kSlots * 16;
+  }
+  // Two 16-bit values as the contraction's dword: x's and y's element j of
+  // their 8 (v_perm byte selection)
+  static __device__ __forceinline__ uint32_t pick2(uint32_t x, uint32_t y, int odd) {
+    return __builtin_amdgcn_perm(y, x, odd ? 0x07060302u : 0x05040100u);
+  }
+
+  // The lane's operand of slot `slot` (streamed variant): one 2-byte load
+  // per element.
   __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, Frag& dst, bool nt) {
-    const int R4 = a.R4;
-    const uint16_t* ap = reinterpret_cast<const uint16_t*>(a.A) +
-                         ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + slot) * 16 + (ln & 15);
+    const int idx = a16_index(slot_pos(slot), ln & 15);
     uint32_t v[8 * NS];
 #pragma unroll
     for (int t = 0; t < 8 * NS; ++t) {
       if (t < MAXR) {
-        const int tt = t < R4 ? t : R4 - 1;
-        const uint32_t x = nt ? (uint32_t)__builtin_nontemporal_load(ap + tt * kSlots * 16)
-                              : (uint32_t)ap[tt * kSlots * 16];
-        uint32_t keep = (t < R4 && (ln >> 4) * R4 + t < a.R) ? 0xffffu : 0u;
-        asm("" : "+v"(keep));
-        v[t] = x & keep;
+        const uint16_t* bp = ring_block(a, tile, t, ln) + idx;
+        const uint32_t x = nt ? (uint32_t)__builtin_nontemporal_load(bp) : (uint32_t)*bp;
+        v[t] = x & keep_mask(a, t, ln);
       } else {
         v[t] = 0u;
       }
@@ -312,10 +324,36 @@ struct Half16Contract {
     }
   }
 
+  // RES: the operand of all the wave's slots w + 8 i.  Per element t, two
+  // 16-byte loads (the interleaved runs 2 w and 2 w + 1) give slots i < 8
+  // and i >= 8; the dwords are then regrouped per slot.
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
+      static_assert(NW == 8, "the interleaved runs hold 8 slots of each of 8 waves");
+      const int k = ln & 15;
 #pragma unroll
-      for (int i = 0; i < SPW; ++i) fetch(a, tile, w + NW * i, ln, areg[i], true);
+      for (int hh = 0; hh < 2; ++hh) {
+        u32x4 u[8 * NS];
+#pragma unroll
+        for (int t = 0; t < 8 * NS; ++t) {
+          if (t < MAXR) {
+            const u32x4* bp = reinterpret_cast<const u32x4*>(ring_block(a, tile, t, ln) + a16_index(16 * w + 8 * hh, k));
+            u[t] = __builtin_nontemporal_load(bp) & keep_mask(a, t, ln);
+          } else {
+            u[t] = u32x4{0u, 0u, 0u, 0u};
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          Frag& f = areg[8 * hh + j];
+#pragma unroll
+          for (int d = 0; d < 4 * NF; ++d) f.f[d / 4][d % 4] = pick2(u[2 * d][j >> 1], u[2 * d + 1][j >> 1], j & 1);
+          if constexpr (NARROW) {
+            f.t[0] = pick2(u[8][j >> 1], u[9][j >> 1], j & 1);
+            f.t[1] = pick2(u[10][j >> 1], u[11][j >> 1], j & 1);
+          }
+        }
+      }
     }
   }
 

@@ -149,7 +149,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       const bool slot_major = a.a_layout == kSlotMajor, perm = a.a_layout == kRingPerm;
       // 16-bit operand: each value rounded once, as the contraction's matrix
       // cores take it (FP16 scaled by the particle's power of two)
-      const bool half = a.a_layout == kRingMajor16;
+      const bool half = a.a_layout == kRingPerm16;
       const float hscale = (half && a.prec == kFP16) ? fp16_operand_scale(a.maxabs[n]) : 1.f;
       const int ss = slot_major ? a.R4 * 64 : 16;
       float* dst = a.out + (slot_major ? (size_t)tile * kSlots * a.R4 * 64 + ring * 16
@@ -177,6 +177,36 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
           stage[sl * 16 + ((8 + rx) ^ sw)] = h ? hi_b[k] : lo_b[k];
         }
         wave_sync();
+        if (half) {
+          // kRingPerm16: the staged slots 64 h + sl are positions 16 (sl % 8)
+          // + 8 h + sl / 8, i.e. the runs G = 2 w + h (w = sl % 8); lane
+          // (w, k) of chunk c = lane + 64 q writes element k of the 8
+          // positions of run G as one 16-byte store (one row, so a chunk is
+          // written whole or not at all)
+          uint16_t* blk = reinterpret_cast<uint16_t*>(a.out) + (size_t)(tile * 4 * a.R4 + ring) * kSlots * 16;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int cix = lnx + 64 * q, w = cix >> 4, k = cix & 15, row = k & 7;
+            uint32_t u[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              uint32_t pr = 0;
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                const int sl = w + 8 * (2 * jj + b);
+                const float v = stage[sl * 16 + (k ^ ((sl & 3) << 2))] * hscale;
+                const uint32_t bits = a.prec == kFP16 ? __builtin_bit_cast(uint16_t, (_Float16)v)
+                                                      : __builtin_bit_cast(uint16_t, (__bf16)v);
+                pr |= bits << (16 * b);
+              }
+              u[jj] = pr;
+            }
+            if (row >= first && row < last)
+              *reinterpret_cast<uint4*>(blk + a16_index(16 * w + 8 * h, k)) = make_uint4(u[0], u[1], u[2], u[3]);
+          }
+          wave_sync();
+          continue;
+        }
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
           if (perm) {
@@ -194,26 +224,6 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
           }
           const int sl = it * 16 + (lnx >> 2);
           const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
-          if (half) {
-            // the same position in a run of 2-byte elements
-            uint16_t* o16 = reinterpret_cast<uint16_t*>(a.out) + ((size_t)(tile * 4 * a.R4 + ring) * kSlots +
-                                                                  64 * h + sl) * 16 + part * 4;
-            const float vv[4] = {val.x * hscale, val.y * hscale, val.z * hscale, val.w * hscale};
-            uint16_t u[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              u[q] = a.prec == kFP16 ? __builtin_bit_cast(uint16_t, (_Float16)vv[q])
-                                     : __builtin_bit_cast(uint16_t, (__bf16)vv[q]);
-            if (full) {
-              *reinterpret_cast<uint2*>(o16) = make_uint2((uint32_t)u[0] | ((uint32_t)u[1] << 16),
-                                                          (uint32_t)u[2] | ((uint32_t)u[3] << 16));
-            } else {
-#pragma unroll
-              for (int q = 0; q < 4; ++q)
-                if (r0 + q >= first && r0 + q < last) o16[q] = u[q];
-            }
-            continue;
-          }
           float* o = lane_dst + (size_t)(64 * h + 16 * it) * ss;
           if (full) {
             *reinterpret_cast<float4*>(o) = val;

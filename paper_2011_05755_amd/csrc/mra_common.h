@@ -38,17 +38,23 @@ enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 //               operand resident)
 //   kSlotMajor  [slot][ring < 4*R4][16]: each slot's rings contiguous (FP32
 //               4-wave and streamed contractions, which re-read the operand)
-//   kRingMajor16  kRingMajor with 16-bit elements, rounded once by the
-//               resampler in the contraction's type (BF16, or FP16 scaled by
-//               a power of two per particle): the 16-bit forms
-enum ALayout { kRingMajor = 0, kRingPerm = 1, kSlotMajor = 2, kRingMajor16 = 3 };
+//   kRingPerm16  the 16-bit forms: elements rounded once by the resampler in
+//               the contraction's type (BF16, or FP16 scaled by a power of two
+//               per particle), [ring < 4*R4][128 positions][16] per row tile
+//               with slot s at position slot_pos(s) (wave w's slots w + 8 i at
+//               16 w + i) and each run of 8 positions interleaved by element:
+//               element k of position 8 G + j at a16_index(8 G + j, k), so that
+//               one 16-byte load gives a lane element k of 8 of its wave's slots
+enum ALayout { kRingMajor = 0, kRingPerm = 1, kSlotMajor = 2, kRingPerm16 = 3 };
 __host__ __device__ constexpr int slot_pos(int s) { return (s & 7) * 16 + (s >> 3); }
+// 16-bit index of element k of position pos within one (row tile, ring) block
+__host__ __device__ constexpr int a16_index(int pos, int k) { return (pos >> 3) * 128 + k * 8 + (pos & 7); }
 // The layout a correlation launch reads (and the resampler must write).
 __host__ __device__ constexpr int a_layout_for(int prec, int variant) {
-  return prec != kFP32 ? kRingMajor16 : (variant == 0 ? kRingPerm : kSlotMajor);
+  return prec != kFP32 ? kRingPerm16 : (variant == 0 ? kRingPerm : kSlotMajor);
 }
 // bytes per operand element of a layout
-__host__ __device__ constexpr int a_elem_bytes(int layout) { return layout == kRingMajor16 ? 2 : 4; }
+__host__ __device__ constexpr int a_elem_bytes(int layout) { return layout == kRingPerm16 ? 2 : 4; }
 
 // 16-bit reference operand of one (reference tile, slot): NS = ceil(R4 / 8)
 // steps of 8 rings per lane group; with NS >= 2 the last step is stored only
@@ -90,15 +96,15 @@ struct PolarArgs {
   int Lp, pad, cx;     // LDS image side (with zero border), border width, centre
   int r_min;           // radius of ring 0
   int a_layout;        // mode 0: ALayout of the operand
-  int prec;            // kRingMajor16: kBF16 or kFP16
+  int prec;            // kRingPerm16: kBF16 or kFP16
   const float* maxabs; // kFP16: max |pixel| of each particle of the chunk (operand scale)
   const double2* cs64; // (cos, sin)(2 pi j / 256)
-  float* out;          // (mode 0, kRingMajor16: 16-bit elements)
+  float* out;          // (mode 0, kRingPerm16: 16-bit elements)
 };
 
 // Fused contraction + inverse FFT over angle + arg-max.
 struct CorrArgs {
-  const float* A;        // [row tiles][...] in layout a_layout (ALayout; 16-bit elements for kRingMajor16)
+  const float* A;        // [row tiles][...] in layout a_layout (ALayout; 16-bit elements for kRingPerm16)
   int a_layout;
   int n_row_tiles;
   int rows;              // valid rows in the chunk (n * S)
