@@ -7,9 +7,12 @@
 // ran 10 % slower).  The image is staged once in LDS with a zero
 // border (coalesced HBM read), beside a float-float cos/sin table; the
 // (ring, 8-row group) items of the particle are split between the waves.
-// In an item, lane (l, row) takes the 32 samples p[16 n1 + 2l + e] of shift
-// `row`, positions computed from the table (integer shifts move the
-// bilinear taps by whole pixels), so the item loop issues no memory loads.
+// In an item, lane (l, row) needs the 32 samples p[16 n1 + 2l + e] of shift
+// `row`; integer shifts move the bilinear taps by whole pixels, so each of
+// the 8 lanes of group l computes the positions and weights of 4 of those
+// angles (from the table: the item loop issues no memory loads) and samples
+// them at all 8 shifts, and a transpose through LDS regroups the samples by
+// shift.
 // The 256-point real FFT runs as a 16 x 8 complex FFT across the eight
 // lanes l of a shift, with a transpose through a per-wave LDS scratch, and
 // the spectra are staged there again so that an item's 128 slots of one
@@ -28,6 +31,13 @@ namespace mra {
 __device__ __forceinline__ int xcd_item() {
   const int per_xcd = gridDim.x / 8;
   return (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+}
+
+// lane J's value of each group of 8 consecutive lanes, to all 8
+// (ds_swizzle bit-mask mode: source lane = (lane & 0x18) | J within 32)
+template <int J>
+__device__ __forceinline__ int group_bcast(int v) {
+  return __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));
 }
 
 template <int MODE>
@@ -70,13 +80,43 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
     const int sc = s < 0 ? 0 : (s < a.S ? s : a.S - 1);
     const int o4 = 4 * (base + shift_offset(sc, a.S1, s1m, a.T, a.Lp));
 
-    // 32 bilinear samples p[16 n1 + 2 l + e] of this lane's shift, the
-    // positions taken from the staged cos/sin (no memory loads in the loop)
+    // 32 bilinear samples v[i] = p[16 n1 + 2 l + e] (i = 2 n1 + e) of this
+    // lane's shift, the positions taken from the staged cos/sin (no memory
+    // loads in the loop).  Positions and weights do not depend on the shift:
+    // lane rx of group l takes them for the angles i = rx (mod 8) and
+    // samples those at all 8 shifts of the item; a transpose through the
+    // wave's scratch, in two halves of 16 angles, hands each lane its own
+    // shift's samples.
     const float rr = (float)(a.r_min + ring);
     const CosSin* cp = cs + 2 * lx;
+    // byte offsets of the item's 8 shifts (lane j of the group computed shift j's)
+    const int o4s[8] = {group_bcast<0>(o4), group_bcast<1>(o4), group_bcast<2>(o4), group_bcast<3>(o4),
+                        group_bcast<4>(o4), group_bcast<5>(o4), group_bcast<6>(o4), group_bcast<7>(o4)};
+    float* tr = reinterpret_cast<float*>(my);  // [64 (l, shift)][17]: row pitch 17 spreads the banks
     float v[32];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = polar_tap(img, o4, Lp4, rr, cp[16 * (i >> 1) + (i & 1)]);
+    for (int hf = 0; hf < 2; ++hf) {
+      float smp[2][8];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = 16 * hf + 8 * b + rx;
+        const CosSin c = cp[16 * (i >> 1) + (i & 1)];
+        const int off = polar_offset(rr, c, Lp4);
+        float w00, w10, w01, w11;
+        polar_weights(rr, c, w00, w10, w01, w11);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) smp[b][j] = bilin4w(img, o4s[j] + off, Lp4, w00, w10, w01, w11);
+      }
+      wave_sync();  // the scratch's earlier readers are done
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tr[(lx * 8 + j) * 17 + 8 * b + rx] = smp[b][j];
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[16 * hf + q] = tr[(lx * 8 + rx) * 17 + q];
+    }
+    wave_sync();  // before the FFT's transposes reuse the scratch
 
     if (MODE == 1) {
       if (valid) {

@@ -79,19 +79,37 @@ __device__ __forceinline__ int shift_offset(int s, int S1, int m, int T, int Lp)
   return __mul24(q, Lp - S1) + s - T * (Lp + 1);
 }
 
-// Bilinear sample of the staged image at offset rr (cos, sin) of angle entry
-// c from the pixel at byte offset o4 (centre plus shift).  Floor and
-// fractions come from the float-float cos/sin: each fraction is within a
-// few FP32 ulps of the one the FP64 position gives.  Where the position lies
-// within rounding of a pixel boundary, floor(rr * ch) can be one off the
-// exact floor; the fraction is then just outside [0, 1), the sample is the
-// same up to rounding, and the taps reach one pixel further, which the zero
-// border of the staged image allows for.
-__device__ __forceinline__ float polar_tap(const float* img, int o4, int Lp4, float rr, const CosSin& c) {
+// Bilinear taps of the staged image at offset rr (cos, sin) of angle entry
+// c from a shift's centre pixel.  Floor and fractions come from the
+// float-float cos/sin: each fraction is within a few FP32 ulps of the one
+// the FP64 position gives.  Where the position lies within rounding of a
+// pixel boundary, floor(rr * ch) can be one off the exact floor; the
+// fraction is then just outside [0, 1), the sample is the same up to
+// rounding, and the taps reach one pixel further, which the zero border of
+// the staged image allows for.  Integer shifts move the taps by whole
+// pixels, so one position split serves every shift: the byte offset of the
+// top-left tap from the shift's centre pixel, and the four weights.
+__device__ __forceinline__ int polar_offset(float rr, const CosSin& c, int Lp4) {
+  const float xf = floorf(rr * c.ch), yf = floorf(rr * c.sh);
+  return __mul24((int)yf, Lp4) + 4 * (int)xf;
+}
+__device__ __forceinline__ void polar_weights(float rr, const CosSin& c, float& w00, float& w10, float& w01,
+                                              float& w11) {
   const float xf = floorf(rr * c.ch), yf = floorf(rr * c.sh);
   const float fx = fmaf(rr, c.cl, fmaf(rr, c.ch, -xf));
   const float fy = fmaf(rr, c.sl, fmaf(rr, c.sh, -yf));
-  return bilin4(img, o4 + __mul24((int)yf, Lp4) + 4 * (int)xf, Lp4, fx, fy);
+  const float gx = 1.f - fx, gy = 1.f - fy;
+  w00 = gx * gy;
+  w10 = fx * gy;
+  w01 = gx * fy;
+  w11 = fx * fy;
+}
+__device__ __forceinline__ float bilin4w(const float* img, int o4, int Lp4, float w00, float w10, float w01,
+                                         float w11) {
+  const char* p = reinterpret_cast<const char*>(img) + o4;
+  const float i00 = *reinterpret_cast<const float*>(p), i10 = *reinterpret_cast<const float*>(p + 4);
+  const float i01 = *reinterpret_cast<const float*>(p + Lp4), i11 = *reinterpret_cast<const float*>(p + Lp4 + 4);
+  return fmaf(w11, i11, fmaf(w01, i01, fmaf(w10, i10, w00 * i00)));
 }
 
 __device__ __forceinline__ float bilin(const float* img, int o, int Lp, float fx, float fy) {
