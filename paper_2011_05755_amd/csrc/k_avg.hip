@@ -10,7 +10,8 @@
 //   3. particles are scattered into class order (stable; one workgroup per
 //      block of 1024 particles);
 //   4. one workgroup per chunk stages each image in LDS (coalesced read),
-//      warps it and accumulates in FP64 registers;
+//      warps it and accumulates the chunk (at most kAvgChunk particles) in
+//      FP32 registers;
 //   5. per class and pixel the chunk sums are added in chunk order and
 //      divided by the count; classes without members keep their image.
 #include "mra_common.h"
@@ -167,66 +168,82 @@ __global__ __launch_bounds__(kAvgThreads) void k_avg_accum(AvgArgs a) {
   // the image sits in LDS with a zero border, one pixel before and two after
   // each row and column: positions clamped to [-1, L] then need no bounds
   // tests (a clamped position lands on border taps, as zero as the pixels
-  // outside the box, and inside the box nothing changes)
+  // outside the box, and inside the box nothing changes).  One more cell
+  // past the image takes the staging writes of a thread's slots beyond the
+  // L x L pixels, so that no pixel loop branches.
   const int Lb = L + 3;
-  for (int i = threadIdx.x; i < Lb * Lb; i += kAvgThreads) img[i] = 0.f;
+  const int spare = Lb * Lb;
+  for (int i = threadIdx.x; i <= spare; i += kAvgThreads) img[i] = 0.f;
   // each thread's pixels u = tid + i * kAvgThreads; the next particle's
   // pixels are loaded into registers while the current one is warped
+  // (slots past the image re-read the last pixel: their value goes to the
+  // spare cell, and the loads stay unconditional)
   float nxt[PPT];
   auto fetch = [&](int pi) {
-    const float* src = a.parts + (size_t)a.order[pi] * L2;
+    const float* src = a.parts + (size_t)__builtin_amdgcn_readfirstlane(a.order[pi]) * L2;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-      const int u = threadIdx.x + i * kAvgThreads;
-      nxt[i] = u < L2 ? __builtin_nontemporal_load(src + u) : 0.f;
+      // (the offset is opaque so that the 64-bit addresses are formed per
+      // load, not kept in registers across the particle loop)
+      uint32_t u = threadIdx.x + i * kAvgThreads;
+      u = u < (uint32_t)L2 ? u : L2 - 1;
+      asm volatile("" : "+v"(u));
+      nxt[i] = __builtin_nontemporal_load(src + u);
     }
   };
-  // (row << 16) | column of the thread's pixels, kept packed; the values
-  // derived from them are recomputed per particle (made opaque below)
-  // rather than held in registers across the particle loop
+  // Per pixel slot: (row << 16) | column (pixel (0, 0) for slots past the
+  // image), and the LDS index of its staging cell (the spare one past the
+  // image).  The packed coordinates are unpacked per particle (made opaque
+  // below) rather than held as floats across the particle loop.
   uint32_t rc[PPT];
+  int cell[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int u = threadIdx.x + i * kAvgThreads;
-    rc[i] = u < L2 ? ((uint32_t)(u / L) << 16) | (uint32_t)(u % L) : 0xffffffffu;
+    const int row = u < L2 ? u / L : 0, col = u < L2 ? u % L : 0;
+    rc[i] = ((uint32_t)row << 16) | (uint32_t)col;
+    cell[i] = u < L2 ? (row + 1) * Lb + col + 1 : spare;
   }
-  double acc[PPT];
+  const float Lf = (float)L, Lbf = (float)Lb;
+  const float* img1 = img + Lb + 1;  // pixel (0, 0)
+  // each chunk (at most kAvgChunk particles) is summed in FP32; the chunk
+  // sums are added in FP64 by k_avg_final
+  float acc[PPT];
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) acc[i] = 0.0;
+  for (int i = 0; i < PPT; ++i) acc[i] = 0.f;
   if (start < end) fetch(start);
   for (int pi = start; pi < end; ++pi) {
-    const int n = a.order[pi];
+    const int n = __builtin_amdgcn_readfirstlane(a.order[pi]);
     __syncthreads();  // the previous particle's warp has finished reading img
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      uint32_t r = rc[i];
-      asm volatile("" : "+v"(r));
-      if (r != 0xffffffffu) img[((int)(r >> 16) + 1) * Lb + (int)(r & 0xffffu) + 1] = nxt[i];
-    }
+    for (int i = 0; i < PPT; ++i) img[cell[i]] = nxt[i];
     __syncthreads();
     if (pi + 1 < end) fetch(pi + 1);
     // sample position c + s + Mir^m Rot(psi)(u - c), in FP32 (positions are
-    // below 2^8, so the bilinear fractions carry ~1e-5 px of rounding)
+    // below 2^8, so the bilinear fractions carry ~1e-5 px of rounding):
+    //   X = ox + cs vx - sn vy,  Y = oy + m (sn vx + cs vy),  (vx, vy) = (col, row) - c
+    // with the centre folded into the offsets
     const double2 cs64 = a.cs64[a.psi[n] & 255];
     const float cs = (float)cs64.x, sn = (float)cs64.y;
-    const float ox = (float)(a.cx + a.shift_x[n]), oy = (float)(a.cx + a.shift_y[n]);
     const float msign = a.mirror[n] ? -1.f : 1.f;
+    const float cxf = (float)a.cx;
+    const float msn = msign * sn, mcs = msign * cs;
+    const float ox = (float)(a.cx + a.shift_x[n]) - (cs - sn) * cxf;
+    const float oy = (float)(a.cx + a.shift_y[n]) - (msn + mcs) * cxf;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       uint32_t r = rc[i];
       asm volatile("" : "+v"(r));
-      if (r != 0xffffffffu) {
-        const float vx = (float)((int)(r & 0xffffu) - a.cx), vy = (float)((int)(r >> 16) - a.cx);
-        const float X = fminf(fmaxf(ox + (cs * vx - sn * vy), -1.f), (float)L);
-        const float Y = fminf(fmaxf(oy + msign * (sn * vx + cs * vy), -1.f), (float)L);
-        const float x0 = floorf(X), y0 = floorf(Y);
-        const float fx = X - x0, fy = Y - y0;
-        const int o = ((int)y0 + 1) * Lb + (int)x0 + 1;
-        const float i00 = img[o], i10 = img[o + 1], i01 = img[o + Lb], i11 = img[o + Lb + 1];
-        const float top = i00 + fx * (i10 - i00);
-        const float bot = i01 + fx * (i11 - i01);
-        acc[i] += (double)(top + fy * (bot - top));
-      }
+      const float col = (float)(r & 0xffffu), row = (float)(r >> 16);
+      const float X = __builtin_amdgcn_fmed3f(fmaf(cs, col, fmaf(-sn, row, ox)), -1.f, Lf);
+      const float Y = __builtin_amdgcn_fmed3f(fmaf(msn, col, fmaf(mcs, row, oy)), -1.f, Lf);
+      const float x0 = floorf(X), y0 = floorf(Y);
+      const float fx = X - x0, fy = Y - y0;
+      const int o = (int)fmaf(y0, Lbf, x0);  // exact: |y0 Lb + x0| < 2^24
+      const float i00 = img1[o], i10 = img1[o + 1], i01 = img1[o + Lb], i11 = img1[o + Lb + 1];
+      const float top = i00 + fx * (i10 - i00);
+      const float bot = i01 + fx * (i11 - i01);
+      acc[i] += top + fy * (bot - top);
     }
   }
   float* out = a.partial + (size_t)c * L2;
@@ -258,7 +275,7 @@ hipError_t launch_averages(const AvgArgs& a, hipStream_t st) {
   else
     hipLaunchKernelGGL(k_avg_scatter, dim3(a.n_blk), dim3(64), (size_t)a.K * sizeof(int), st, a);
   const int L2 = a.L * a.L;
-  const size_t lds = (size_t)(a.L + 3) * (a.L + 3) * sizeof(float);
+  const size_t lds = ((size_t)(a.L + 3) * (a.L + 3) + 1) * sizeof(float);
   const int ppt = (L2 + kAvgThreads - 1) / kAvgThreads;
   dim3 g(a.max_chunks), b(kAvgThreads);
   if (ppt <= 16) hipLaunchKernelGGL(k_avg_accum<16>, g, b, lds, st, a);
