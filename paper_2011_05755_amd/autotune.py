@@ -1,15 +1,22 @@
 """Autotuner for the tile configuration of the correlation kernel.
 
-A refset's tile configuration is (corr_variant, chunk_particles); see
-``mra_tuning`` in include/mra.h.  No configuration changes any result, only
-speed, so the tuner may pick freely among the ones the library accepts.
+A refset's tile configuration is (corr_variant, chunk_particles, run_tiles);
+see ``mra_tuning`` in include/mra.h.  No configuration changes any result,
+only speed, so the tuner may pick freely among the ones the library accepts.
+The tile itself (8 particle rows by 8 references) is fixed by the matrix-core
+block, whose 16 columns are the 8 references' two spectrum combinations, and
+by the LDS state of its 64 pairs; what a workgroup covers is tunable through
+run_tiles, the number of consecutive row tiles it takes (they share the
+particle thresholds of the pruning bound, and fewer, longer runs trade
+launch tail for pruning reach).
 
 Key:        (L, number of rings, K bucket, T, precision), where the K bucket is
             the smallest power of two >= K (at least 8, one reference tile).
 Candidates: every variant that ``mra_set_tuning`` accepts for the refset,
             crossed with a few chunk sizes (0 = as large as the workspace
             allows; small chunks keep the particle operand of a chunk within
-            the last-level cache).
+            the last-level cache), with the library's own run length; then,
+            at the winner, a few run lengths (0 = the library's choice).
 Measure:    the median wall time of ``mra_align`` on a sample stack,
             synchronised, after one untimed call per candidate.
 Cache:      a JSON file, ``$MRA_AUTOTUNE_CACHE`` or
@@ -30,6 +37,7 @@ import time
 from typing import Callable, Iterable
 
 DEFAULT_CHUNKS = (0, 128, 512, 2048)
+DEFAULT_RUNS = (0, 1, 2, 4, 8)
 MAX_VARIANT = 4   # variant ids are probed from 0 up to this bound
 
 
@@ -120,7 +128,7 @@ def wall_ms(ctx, refset_id: int, parts, reps: int) -> float:
 
 
 def tune(ctx, refset_id: int, parts, reps: int = 3, cache: Cache | None = None,
-         chunks: Iterable[int] = DEFAULT_CHUNKS,
+         chunks: Iterable[int] = DEFAULT_CHUNKS, runs: Iterable[int] = DEFAULT_RUNS,
          timer: Callable[[object, int, object, int], float] = wall_ms, log=None) -> dict:
     """Time every candidate on `parts`, apply the fastest to the refset and
     record it in `cache` (if given; the caller saves).  Returns the entry."""
@@ -134,9 +142,21 @@ def tune(ctx, refset_id: int, parts, reps: int = 3, cache: Cache | None = None,
         if log:
             log(f"{key}: variant {v} chunk {c}: {times[(v, c)]:.3f} ms")
     (bv, bc) = min(times, key=lambda vc: (times[vc], vc))
-    ctx.set_tuning(refset_id, corr_variant=bv, chunk_particles=bc)
-    entry = dict(corr_variant=bv, chunk_particles=bc, ms=times[(bv, bc)], n_sample=n,
-                 candidates={f"{v}/{c}": round(t, 4) for (v, c), t in sorted(times.items())})
+    # the run length at the winner (run_tiles 0, the library's choice, is the
+    # time already taken)
+    run_times = {0: times[(bv, bc)]}
+    for r in runs:
+        if r in run_times:
+            continue
+        ctx.set_tuning(refset_id, corr_variant=bv, chunk_particles=bc, run_tiles=r)
+        run_times[r] = timer(ctx, refset_id, parts, reps)
+        if log:
+            log(f"{key}: variant {bv} chunk {bc} run {r}: {run_times[r]:.3f} ms")
+    br = min(run_times, key=lambda r: (run_times[r], r))
+    ctx.set_tuning(refset_id, corr_variant=bv, chunk_particles=bc, run_tiles=br)
+    entry = dict(corr_variant=bv, chunk_particles=bc, run_tiles=br, ms=run_times[br], n_sample=n,
+                 candidates={f"{v}/{c}": round(t, 4) for (v, c), t in sorted(times.items())},
+                 runs={str(r): round(t, 4) for r, t in sorted(run_times.items())})
     if cache is not None:
         cache.put(key, entry)
     return entry
@@ -147,7 +167,8 @@ def apply(ctx, refset_id: int, cache: Cache) -> bool:
     e = cache.get(refset_key(ctx, refset_id))
     if e is None:
         return False
-    ctx.set_tuning(refset_id, corr_variant=int(e["corr_variant"]), chunk_particles=int(e["chunk_particles"]))
+    ctx.set_tuning(refset_id, corr_variant=int(e["corr_variant"]), chunk_particles=int(e["chunk_particles"]),
+                   run_tiles=int(e.get("run_tiles", 0)))
     return True
 
 

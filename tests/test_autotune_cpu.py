@@ -19,12 +19,14 @@ class FakeCtx:
     def __init__(self):
         self.refsets = {3: FakeRefset(96, 46, 37, 2, "fp32")}
         self.tuning = {3: (2, 0)}
+        self.run = {3: 0}
 
-    def set_tuning(self, rid, corr_variant=-1, chunk_particles=0):
+    def set_tuning(self, rid, corr_variant=-1, chunk_particles=0, run_tiles=0):
         v = 2 if corr_variant < 0 else corr_variant
-        if v not in (0, 2) or chunk_particles < 0:
+        if v not in (0, 2) or chunk_particles < 0 or not 0 <= run_tiles <= 64:
             raise mra.MRAError(mra.MRA_E_INVAL, "variant cannot serve this geometry")
         self.tuning[rid] = (v, chunk_particles)
+        self.run[rid] = run_tiles
 
     def get_tuning(self, rid):
         return self.tuning[rid]
@@ -52,7 +54,13 @@ def test_tune_picks_the_fastest_applies_it_and_caches(tmp_path):
     cost = {(0, 0): 5.0, (0, 128): 4.0, (0, 512): 4.5, (2, 0): 3.0, (2, 128): 3.5, (2, 512): 3.0}
     seen = []
 
+    run_cost = {1: 3.2, 2: 2.5, 4: 2.5, 8: 2.9}     # run 0 (the library's choice) costs cost[...]
+
     def timer(c, rid, parts, reps):
+        r = c.run[rid]
+        if r:
+            assert c.get_tuning(rid) == (2, 0)     # run lengths are timed at the winner
+            return run_cost[r]
         seen.append(c.get_tuning(rid))
         return cost[c.get_tuning(rid)]
 
@@ -60,15 +68,18 @@ def test_tune_picks_the_fastest_applies_it_and_caches(tmp_path):
     e = autotune.tune(ctx, 3, Parts(), cache=cache, chunks=(0, 128, 512, 2048), timer=timer)
     assert sorted(seen) == sorted(cost)            # chunk 2048 >= sample size is skipped
     assert (e["corr_variant"], e["chunk_particles"]) == (2, 0)   # tie broken towards the smaller config
-    assert ctx.get_tuning(3) == (2, 0)
+    assert e["run_tiles"] == 2 and e["ms"] == 2.5                # tie broken towards the shorter run
+    assert ctx.get_tuning(3) == (2, 0) and ctx.run[3] == 2
     cache.save()
     data = json.loads((tmp_path / "t.json").read_text())
     assert data["L96-R46-K64-T2-fp32"]["candidates"]["0/128"] == 4.0
 
+    assert data["L96-R46-K64-T2-fp32"]["runs"] == {"0": 3.0, "1": 3.2, "2": 2.5, "4": 2.5, "8": 2.9}
+
     ctx2 = FakeCtx()
     ctx2.set_tuning(3, corr_variant=0)
     assert autotune.apply(ctx2, 3, autotune.Cache(str(tmp_path / "t.json")))
-    assert ctx2.get_tuning(3) == (2, 0)
+    assert ctx2.get_tuning(3) == (2, 0) and ctx2.run[3] == 2
     ctx2.refsets[3].K = 500
     assert not autotune.apply(ctx2, 3, autotune.Cache(str(tmp_path / "t.json")))
 
