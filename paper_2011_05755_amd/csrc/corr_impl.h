@@ -255,8 +255,9 @@ struct Fp32Contract {
 };
 
 // Contraction with 16-bit operands; NS = ceil(MAXR / 8) <= 2 steps of 8
-// rings per lane group, R4 <= MAXR (EXACT: every work item has
-// ceil(R4 / 8) == NS).  With MAXR = 12 the second step holds at most 4 rings
+// rings per lane group, R4 <= MAXR (EXACT: every work item's R4 lies in the
+// bucket MAXR - 3 .. MAXR, or 1 .. 8 for MAXR = 8: ceil(R4 / 8) == NS, and at
+// MAXR = 16 the reference operand's last step is 8 wide).  With MAXR = 12 the second step holds at most 4 rings
 // per lane group (NARROW): the resident particle operand keeps 2 dwords of it
 // per slot instead of 4.  The particle operand
 // arrives rounded to the contraction's type (FP16 already scaled per
@@ -376,7 +377,11 @@ struct Half16Contract {
         if constexpr (NARROW) {
 #pragma unroll
           for (int j = 0; j < 2; ++j) dst.t[j] = tp[j < h ? j : h - 1];
+        } else if constexpr (EXACT) {
+          dst.f[1] = *reinterpret_cast<const u32x4*>(tp);  // 8 wide: one 16-byte load
         } else {
+          // (four 4-byte loads cost the address path four times one 16-byte
+          // load: batched launches keep the ring buckets apart to avoid this)
 #pragma unroll
           for (int j = 0; j < 4; ++j) dst.f[1][j] = tp[j < h ? j : h - 1];
         }
@@ -894,18 +899,18 @@ inline void corr_go(const CorrArgs* a, bool table, const CorrBatch* b, int grid,
   else launch_one<C>(*a, table, st);
 }
 
-// 16-bit forms: operand ring bucket MAXR in {8, 12, 16}; exact step count
-// where every work item has the same one.
+// 16-bit forms: operand ring bucket MAXR in {8, 12, 16} (R4 <= 8, 9..12,
+// 13..16); exact where every work item lies in the bucket (then the step
+// count is fixed, and at 16 the last step is 8 wide), else the run-time form.
 template <int PREC, bool RES>
 inline void corr_dispatch_16(int r4min, int r4max, const CorrArgs* a, bool table, const CorrBatch* b, int grid,
                              hipStream_t st) {
-  const bool ex = (r4min + 7) / 8 == (r4max + 7) / 8;
   if (r4max <= 8) return corr_go<Cfg<PREC, 8, 8, RES, true>>(a, table, b, grid, st);
   if (r4max <= 12) {
-    if (ex) return corr_go<Cfg<PREC, 8, 12, RES, true>>(a, table, b, grid, st);
+    if (r4min > 8) return corr_go<Cfg<PREC, 8, 12, RES, true>>(a, table, b, grid, st);
     return corr_go<Cfg<PREC, 8, 12, RES, false>>(a, table, b, grid, st);
   }
-  if (ex) return corr_go<Cfg<PREC, 8, 16, RES, true>>(a, table, b, grid, st);
+  if (r4min > 12) return corr_go<Cfg<PREC, 8, 16, RES, true>>(a, table, b, grid, st);
   return corr_go<Cfg<PREC, 8, 16, RES, false>>(a, table, b, grid, st);
 }
 

@@ -630,14 +630,19 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
 
 void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Plan>& plans) {
   const uint64_t budget = c->cap / 2;
-  // stacks that share a correlation instantiation (precision, tile variant)
-  // are packed into the same waves; within a group the caller's order holds
+  // stacks that share a correlation instantiation (precision, tile variant,
+  // and for the 16-bit forms the ring bucket: launches that mix buckets take
+  // the kernel's slower run-time form) are packed into the same waves;
+  // within a group the caller's order holds
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
+  auto group = [](const Refset& rs) {
+    const int bucket = rs.g.precision == kFP32 ? 0 : (rs.R4 <= 8 ? 0 : (rs.R4 <= 12 ? 1 : 2));
+    return (rs.g.precision * 16 + rs.variant) * 4 + bucket;
+  };
   auto key = [&](int i) {
     if (stacks[i].N <= 0) return 0;
-    const Refset& rs = get_refset(c, stacks[i].refset_id);
-    return rs.g.precision * 16 + rs.variant;
+    return group(get_refset(c, stacks[i].refset_id));
   };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
   std::vector<Piece> wave;
@@ -662,8 +667,7 @@ void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Pla
     const uint64_t per = (uint64_t)p.S * a_bytes_per_row(rs);
     const int64_t cap_n = rs.chunk > 0 ? rs.chunk : std::max<int64_t>(1, (int64_t)(budget / per));
     for (int64_t n0 = 0; n0 < s.N;) {
-      const bool compatible = wave.empty() || (wave[0].rs->g.precision == rs.g.precision &&
-                                               wave[0].rs->variant == rs.variant);
+      const bool compatible = wave.empty() || group(*wave[0].rs) == group(rs);
       if (!compatible || (int)wave.size() == kMaxBatchPieces || used + per > budget) {
         if (!wave.empty()) launch_wave(c, stacks, wave);
         wave.clear();
