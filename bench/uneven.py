@@ -76,7 +76,7 @@ def main(argv=None) -> int:
                     e = cache.get(key)
                     if e is None:
                         e = autotune.tune(ctx, base + i, parts[:args.tune_sample], reps=2, cache=cache,
-                                          chunks=(0, 128))
+                                          chunks=(0, 128), log=log)
                     tuned[key] = e
                 autotune.apply(ctx, base + i, cache)
             cache.save()
@@ -112,14 +112,16 @@ def main(argv=None) -> int:
         variants = {}
         for i in range(len(data)):
             v, c = ctx.get_tuning(base + i)
-            variants[f"{v}/{c}"] = variants.get(f"{v}/{c}", 0) + 1
+            e = cache.get(autotune.refset_key(ctx, base + i)) or {}
+            k = f"{v}/{c}/run{e.get('run_tiles', 0)}"
+            variants[k] = variants.get(k, 0) + 1
         line = dict(workload=f"uneven stacks: {len(data)} stacks, L in {{64,76,96,128}}, N 2k..50k "
                              f"(x{args.n_scale}), K 20..400, shifts +-2..+-5, own refset each, seed {args.seed}",
                     precision=form, particles=n_total, batch_s=round(t_batch, 4),
                     particles_per_s=round(n_total / t_batch, 1),
                     per_stack_calls_s=None if t_single is None else round(t_single, 4),
                     identical_to_per_stack_calls=None if same is None else f"{same}/{len(data)}",
-                    tuned_keys=len(tuned), tune_s=round(t_tune, 2), variant_chunk_counts=variants)
+                    tuned_keys=len(tuned), tune_s=round(t_tune, 2), variant_chunk_run_counts=variants)
         print(json.dumps(line), flush=True)
         for i in range(len(data)):
             ctx.unload_refs(base + i)
