@@ -639,143 +639,159 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
       if ((live >> ln) & 1) list[rank] = ln;
       lds_wave_sync();
     }
-    // The wave's inverse-FFT columns (pass 1) and rows (pass 2) are
-    // CPW * w + c, c = 0 .. CPW-1: lane group c (LPC lanes) takes column /
-    // row c for the live pairs list[n0 + ln % LPC].  Waves 0 .. NW/2-1 hold
+    // The inverse FFT of the live pairs.  With CPWX columns (pass 1) and
+    // rows (pass 2) per wave, the working waves' columns / rows are
+    // CPWX * w + c, c = 0 .. CPWX-1: lane group c (LPCX lanes) takes column /
+    // row c for the live pairs list[n0 + ln % LPCX].  The first waves hold
     // rows below 8 and the others rows from 8 on, so that every wave's
     // pass-2 addresses share one shape (a lane base plus constant offsets).
-    constexpr int LPC = 64 / CPW;
+    // At most 16 live pairs (most reference tiles) fit 4 columns of 16
+    // lanes per wave: then waves 0..3 (one per SIMD) do the passes and the
+    // others wait at the barriers, so each SIMD issues one wave's
+    // instructions instead of two.
+    auto passes = [&](auto cpw_c) {
+      constexpr int CPWX = decltype(cpw_c)::value, LPCX = 64 / CPWX;
+      const bool work = CPWX * w < 16;  // wave-uniform
 
-    // ---------------- inverse FFT over angle, pass 1 ----------------
-    // H_j (j = 16 k1 + k2) of pair P: half 0 of slot j (j < 128) or half 1
-    // of slot 256 - j (j >= 128; slot 0 for j = 128)
-    {
+      // ---------------- inverse FFT over angle, pass 1 ----------------
+      // H_j (j = 16 k1 + k2) of pair P: half 0 of slot j (j < 128) or half 1
+      // of slot 256 - j (j >= 128; slot 0 for j = 128)
+      if (work) {
 #pragma unroll 1
-      for (int n0 = 0; n0 < n_live; n0 += LPC) {
-        // lane-derived values are recomputed here rather than kept live
-        // across the reference loop, where the registers hold the operand
-        int lnx = ln;
-        asm volatile("" : "+v"(lnx));
-        const int lane_n = lnx % LPC, k2 = CPW * w + lnx / LPC;
-        const bool act = n0 + lane_n < n_live;
-        const int P = list[act ? n0 + lane_n : 0];
-        const int lo = k2 * 128 + P, hi = P - k2 * 128;
-        const int mid = k2 == 0 ? 64 + P : hi + 257 * 64;
-        auto at = [&](int k1) { return k1 < 8 ? lo + k1 * 2048 : (k1 == 8 ? mid : hi + (513 - 32 * k1) * 64); };
-        float2 x[16];
+        for (int n0 = 0; n0 < n_live; n0 += LPCX) {
+          // lane-derived values are recomputed here rather than kept live
+          // across the reference loop, where the registers hold the operand
+          int lnx = ln;
+          asm volatile("" : "+v"(lnx));
+          const int lane_n = lnx % LPCX, k2 = CPWX * w + lnx / LPCX;
+          const bool act = n0 + lane_n < n_live;
+          const int P = list[act ? n0 + lane_n : 0];
+          const int lo = k2 * 128 + P, hi = P - k2 * 128;
+          const int mid = k2 == 0 ? 64 + P : hi + 257 * 64;
+          auto at = [&](int k1) { return k1 < 8 ? lo + k1 * 2048 : (k1 == 8 ? mid : hi + (513 - 32 * k1) * 64); };
+          float2 x[16];
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) x[k1] = sm.stc[at(k1)];
-        inv_pass1(k2, x, [&](int e) { return sm.tw[e & 255]; });
-        if (act) {
+          for (int k1 = 0; k1 < 16; ++k1) x[k1] = sm.stc[at(k1)];
+          inv_pass1(k2, x, [&](int e) { return sm.tw[e & 255]; });
+          if (act) {
 #pragma unroll
-          for (int n1 = 0; n1 < 16; ++n1) sm.stc[at(n1)] = x[n1];
+            for (int n1 = 0; n1 < 16; ++n1) sm.stc[at(n1)] = x[n1];
+          }
         }
       }
-    }
-    __syncthreads();
+      __syncthreads();
 
-    // ---------------- pass 2 + arg-max ----------------
-    // Rows below 8 read upwards from slot 16 n1, the others downwards from
-    // slot 256 - 16 n1.  SPLIT: one loop per direction (each wave runs one),
-    // so that either keeps its 16 reads at constant offsets from one address
-    // (in one loop the compiler merges the two read sets into 31 per-element
-    // addresses); the 4-wave kernels, whose registers are full, keep one loop.
-    auto pass2 = [&](auto dir_c) {
-      constexpr int dir = decltype(dir_c)::value;  // 1 up, 2 down, 0 either (chosen per wave)
+      // ---------------- pass 2 + arg-max ----------------
+      // Rows below 8 read upwards from slot 16 n1, the others downwards from
+      // slot 256 - 16 n1.  SPLIT: one loop per direction (each wave runs one),
+      // so that either keeps its 16 reads at constant offsets from one address
+      // (in one loop the compiler merges the two read sets into 31 per-element
+      // addresses); the 4-wave kernels, whose registers are full, keep one loop.
+      auto pass2 = [&](auto dir_c) {
+        constexpr int dir = decltype(dir_c)::value;  // 1 up, 2 down, 0 either (chosen per wave)
 #pragma unroll 1
-      for (int n0 = 0; n0 < n_live; n0 += LPC) {
-        int lnx = ln;
-        asm volatile("" : "+v"(lnx));
-        const int lane_n = lnx % LPC, c = lnx / LPC, n1 = CPW * w + c;
-        const bool act = n0 + lane_n < n_live;
-        const int P = list[act ? n0 + lane_n : 0];
-        const int row_l = P >> 3, ref_l = P & 7;
-        const int row = tile * kRowTile + row_l;
-        const int k = kt * kRefTile + ref_l;
-        float2 x[16];
-        const bool low = dir == 1 || (dir == 0 && CPW * w < 8);
-        if (low) {
-          const int base = n1 * 2048 + P;
+        for (int n0 = 0; n0 < n_live; n0 += LPCX) {
+          int lnx = ln;
+          asm volatile("" : "+v"(lnx));
+          const int lane_n = lnx % LPCX, c = lnx / LPCX, n1 = CPWX * w + c;
+          const bool act = n0 + lane_n < n_live;
+          const int P = list[act ? n0 + lane_n : 0];
+          const int row_l = P >> 3, ref_l = P & 7;
+          const int row = tile * kRowTile + row_l;
+          const int k = kt * kRefTile + ref_l;
+          float2 x[16];
+          const bool low = dir == 1 || (dir == 0 && CPWX * w < 8);
+          if (low) {
+            const int base = n1 * 2048 + P;
 #pragma unroll
-          for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
-        } else if constexpr (dir == 2) {
-          const int base = (513 - 32 * n1) * 64 + P;  // k2 = 0; k2 steps go down by 128
-          int top = base - 15 * 128;                  // k2 = 15, the lowest address
-          asm volatile("" : "+v"(top));               // the base of the reads (not re-associated)
-          x[0] = sm.stc[n1 == 8 ? 64 + P : base];
+            for (int k2 = 0; k2 < 16; ++k2) x[k2] = sm.stc[base + k2 * 128];
+          } else if constexpr (dir == 2) {
+            const int base = (513 - 32 * n1) * 64 + P;  // k2 = 0; k2 steps go down by 128
+            int top = base - 15 * 128;                  // k2 = 15, the lowest address
+            asm volatile("" : "+v"(top));               // the base of the reads (not re-associated)
+            x[0] = sm.stc[n1 == 8 ? 64 + P : base];
 #pragma unroll
-          for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[top + (15 - k2) * 128];
-        } else {
-          const int base = (513 - 32 * n1) * 64 + P;
-          x[0] = sm.stc[n1 == 8 ? 64 + P : base];
+            for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[top + (15 - k2) * 128];
+          } else {
+            const int base = (513 - 32 * n1) * 64 + P;
+            x[0] = sm.stc[n1 == 8 ? 64 + P : base];
 #pragma unroll
-          for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
-        }
-        inv_pass2(x);
-        if constexpr (MODE == kTable) {
-          if (act && row < a.rows && k < a.K) {
-            const int n = row / a.S, s = row - n * a.S;
-            const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
-            for (int m = 0; m < a.M; ++m) {
-              float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
-#pragma unroll
-              for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
-            }
+            for (int k2 = 1; k2 < 16; ++k2) x[k2] = sm.stc[base - k2 * 128];
           }
-        } else {
-          // only values above the row's best of earlier reference tiles can
-          // win (a tie with an earlier tile loses: its flat index is smaller)
-          const float thr = sm.thr[row_l];
-          const bool valid = act && row < a.rows && k < a.K;
-          // the candidate left out of this pass (key m * 256 + angle of this
-          // lane's (row, ref)), or -1
-          int ex = -1;
-          if (MODE == kRunnerUp && valid) {
-            const int n = row / a.S, s = row - n * a.S;
-            const int e = a.excl[n];
-            if (e >= 0) {
-              const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
-              if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
-            }
-          }
-          float bv = -INFINITY;
-          int bi = 0x7fffffff;
-          float mx = -INFINITY;
+          inv_pass2(x);
+          if constexpr (MODE == kTable) {
+            if (act && row < a.rows && k < a.K) {
+              const int n = row / a.S, s = row - n * a.S;
+              const float unscale = PREC == kFP16 ? 1.f / (fp16_scale(a, row) * a.b_scale) : 1.f;
+              for (int m = 0; m < a.M; ++m) {
+                float* o = a.table + ((((size_t)n * a.K + k) * a.M + m) * a.S + s) * kNphi;
 #pragma unroll
-          for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
-          if (MODE == kArgmax && mx > thr) {
-            // the lane's best is mx; its key is the smallest among the
-            // candidates equal to it (keys grow with n2, mirror 1 after 0)
-            bv = mx;
-            if (a.M == 2) {
-#pragma unroll
-              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
-            }
-#pragma unroll
-            for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
-          } else if (MODE == kRunnerUp && mx > thr) {
-#pragma unroll
-            for (int n2 = 0; n2 < 16; ++n2) {
-              const int ang = n1 + 16 * n2;
-              if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
-              if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
-                bv = x[n2].y;
-                bi = 256 + ang;
+                for (int n2 = 0; n2 < 16; ++n2) o[n1 + 16 * n2] = (m ? x[n2].y : x[n2].x) * unscale;
               }
             }
+          } else {
+            // only values above the row's best of earlier reference tiles can
+            // win (a tie with an earlier tile loses: its flat index is smaller)
+            const float thr = sm.thr[row_l];
+            const bool valid = act && row < a.rows && k < a.K;
+            // the candidate left out of this pass (key m * 256 + angle of this
+            // lane's (row, ref)), or -1
+            int ex = -1;
+            if (MODE == kRunnerUp && valid) {
+              const int n = row / a.S, s = row - n * a.S;
+              const int e = a.excl[n];
+              if (e >= 0) {
+                const int rest = e >> 8, se = rest % a.S, km = rest / a.S;
+                if (se == s && km / a.M == k) ex = (km % a.M) * 256 + (e & 255);
+              }
+            }
+            float bv = -INFINITY;
+            int bi = 0x7fffffff;
+            float mx = -INFINITY;
+#pragma unroll
+            for (int n2 = 0; n2 < 16; ++n2) mx = fmaxf(mx, a.M == 2 ? fmaxf(x[n2].x, x[n2].y) : x[n2].x);
+            if (MODE == kArgmax && mx > thr) {
+              // the lane's best is mx; its key is the smallest among the
+              // candidates equal to it (keys grow with n2, mirror 1 after 0)
+              bv = mx;
+              if (a.M == 2) {
+#pragma unroll
+                for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].y == mx ? 256 + n1 + 16 * n2 : bi;
+              }
+#pragma unroll
+              for (int n2 = 15; n2 >= 0; --n2) bi = x[n2].x == mx ? n1 + 16 * n2 : bi;
+            } else if (MODE == kRunnerUp && mx > thr) {
+#pragma unroll
+              for (int n2 = 0; n2 < 16; ++n2) {
+                const int ang = n1 + 16 * n2;
+                if (ang != ex && better(x[n2].x, ang, bv, bi)) { bv = x[n2].x; bi = ang; }
+                if (a.M == 2 && 256 + ang != ex && better(x[n2].y, 256 + ang, bv, bi)) {
+                  bv = x[n2].y;
+                  bi = 256 + ang;
+                }
+              }
+            }
+            if (valid && bi != 0x7fffffff && bv > thr) {
+              const int iota = ((k * a.M + (bi >> 8)) * a.S + row % a.S) * kNphi + (bi & 255);
+              atomicMax(&sm.key[row_l], cand_key(bv, iota));
+            }
           }
-          if (valid && bi != 0x7fffffff && bv > thr) {
-            const int iota = ((k * a.M + (bi >> 8)) * a.S + row % a.S) * kNphi + (bi & 255);
-            atomicMax(&sm.key[row_l], cand_key(bv, iota));
-          }
+        }
+      };
+      if (work) {
+        if constexpr (SPLIT) {
+          if (CPWX * w < 8) pass2(std::integral_constant<int, 1>{});  // wave-uniform
+          else pass2(std::integral_constant<int, 2>{});
+        } else {
+          pass2(std::integral_constant<int, 0>{});
         }
       }
     };
-    if constexpr (SPLIT) {
-      if (CPW * w < 8) pass2(std::integral_constant<int, 1>{});  // wave-uniform
-      else pass2(std::integral_constant<int, 2>{});
+    if constexpr (NW == 8) {
+      if (n_live <= 16) passes(std::integral_constant<int, 4>{});  // workgroup-uniform
+      else passes(std::integral_constant<int, 2>{});
     } else {
-      pass2(std::integral_constant<int, 0>{});
+      passes(std::integral_constant<int, CPW>{});
     }
     __syncthreads();
     // the particle bests of the rows, for the next reference tile's bound
