@@ -121,6 +121,36 @@ def test_tile_variants_and_chunk_sizes_do_not_change_results(ctx, data, precisio
     ctx.set_tuning(rid)   # back to the default
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_run_length_does_not_change_results(ctx, precision):
+    """A workgroup's run of consecutive row tiles carries each particle's best
+    from one tile to the next as a pruning threshold; no run length (one tile
+    each, odd lengths that end inside a particle, the whole chunk) may change
+    any result, in the single, runner-up and batched launches."""
+    from paper_2011_05755_amd import mra
+    L, K, T, N = 64, 21, 2, 37            # 925 rows: 116 row tiles, the last ragged
+    log(f"{precision}: run lengths")
+    blobs = synth.make_blobs(K, L, seed=(66, 0), rho_max=28)
+    refs = synth.render_refs(blobs).to(DEV)
+    parts = synth.make_particles(blobs, N, T, 0.05, seed=(66, 1), device=DEV)[0]
+    rid = 480 + len(precision)
+    ctx.load_refs(rid, refs, r_min=1, r_max=30, shift_max=T, precision=precision)
+    want = ctx.align(rid, parts).to_numpy()
+    want2 = ctx.align(rid, parts, with_cc2=True).to_numpy()
+    for run in (1, 2, 3, 7, 64):
+        ctx.set_tuning(rid, run_tiles=run)
+        same(ctx.align(rid, parts).to_numpy(), want, f"run {run}")
+        same(ctx.align(rid, parts, with_cc2=True).to_numpy(), want2, f"cc2, run {run}")
+        out = mra.AlignResult.empty(N, DEV)
+        ctx.align_batch([(rid, parts, -1, out)])
+        same(out.to_numpy(), want, f"batch, run {run}")
+    ctx.set_tuning(rid)
+    g = oracle.Geometry(L=L, r_min=1, r_max=30, n_phi=256, shift_max=T)
+    ref = oracle.align(parts.cpu().numpy(), refs.cpu().numpy(), g)
+    tol = 1e-5 if precision == "fp32" else 2e-3
+    assert (np.abs(want["cc"] - ref["cc"]) / np.abs(ref["cc"])).max() <= tol
+
+
 def test_batch_cut_into_many_pieces_and_waves(ctx, data):
     from paper_2011_05755_amd import mra
     log("batch cut into more pieces than one launch holds")
