@@ -1,10 +1,16 @@
 """Build libmra.so (HIP kernels for gfx950 + the C ABI) in-tree.
 
     python -m paper_2011_05755_amd.build
+    python -m paper_2011_05755_amd.build --sanitize OUT.so
 
 Every ``csrc/*.hip`` file is compiled to an object in ``_build/`` (in
 parallel) and linked into ``paper_2011_05755_amd/libmra.so``.  The library
 is written next to this file so that it travels with the source tree.
+
+``--sanitize`` builds a separate copy whose host code (the C ABI: validation,
+planning, error handling) carries AddressSanitizer and UndefinedBehavior-
+Sanitizer; device code is built as usual.  It is for CPU-side checks with
+clang's ASan runtime preloaded (``asan_runtime()``), never for GPU runs.
 """
 
 from __future__ import annotations
@@ -44,9 +50,22 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+SANITIZE = ["-O1", "-g",
+            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """clang's shared ASan runtime (for LD_PRELOAD into a host process)."""
+    found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise RuntimeError("clang's ASan runtime not found")
+    return found[-1]
+
+
+def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src).replace(".hip", ".o"))
+    cmd = [hipcc(), *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -70,6 +89,28 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out: str, obj_dir: str | None = None, verbose: bool = False) -> str:
+    """The library with host-side ASan + UBSan, written to `out` (objects in
+    `obj_dir`, by default beside `out`)."""
+    bdir = obj_dir or os.path.join(os.path.dirname(os.path.abspath(out)), "sanitize_obj")
+    os.makedirs(bdir, exist_ok=True)
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    workers = min(len(srcs), max(1, (os.cpu_count() or 2)), 8)
+    with cf.ThreadPoolExecutor(workers) as ex:
+        objs = list(ex.map(lambda s: _compile(s, bdir, SANITIZE), srcs))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", out, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) == 3 and sys.argv[1] == "--sanitize":
+        build_sanitized(sys.argv[2], verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -64,6 +65,53 @@ def test_register_fft_building_blocks_on_cpu(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip() == "ok"
+
+
+_SANITIZED_DRIVER = r"""
+import ctypes, itertools, sys
+lib = ctypes.CDLL(sys.argv[1])
+class Geom(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("L", "r_min", "r_max", "n_phi", "shift_max", "mirror", "precision", "normalize", "rescore_rows")]
+lib.mra_check_geom.argtypes = [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.c_int32]
+lib.mra_strerror.restype = ctypes.c_char_p
+lib.mra_last_error.restype = ctypes.c_char_p
+lib.mra_last_error.argtypes = [ctypes.c_void_p]
+lib.mra_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64]
+lib.mra_destroy.argtypes = [ctypes.c_void_p]
+ok = err = 0
+for L, (r0, r1), T, nphi, K, prec, mirror, rr in itertools.product(
+        (7, 8, 64, 76, 160, 161), ((0, 10), (1, 30), (5, 4), (1, 64), (1, 65), (3, 35)), (-1, 0, 3, 8, 9),
+        (128, 256), (0, 1, 100, 15000, 100000), (0, 1, 2, 3), (0, 1), (-1, 0, 4, 9)):
+    g = Geom(L, r0, r1, nphi, max(T, 0), mirror, prec, 1, rr)
+    rc = lib.mra_check_geom(ctypes.byref(g), K, T)
+    ok += rc == 0
+    err += rc < 0
+for code in range(-8, 2):
+    assert lib.mra_strerror(code)
+h = ctypes.c_void_p()
+assert lib.mra_create(ctypes.byref(h), 0, None, 0) < 0 and not h.value   # no device here
+assert lib.mra_last_error(None) and lib.mra_destroy(None) < 0
+print(f"checked {ok} accepted and {err} rejected geometries")
+"""
+
+
+def test_host_code_under_asan_and_ubsan(tmp_path):
+    """The C ABI's host code built with AddressSanitizer and UndefinedBehavior-
+    Sanitizer (device code unchanged; never run on a GPU): geometry and
+    index-range validation over a grid of valid and invalid geometries, error
+    strings, context creation without a device."""
+    from paper_2011_05755_amd import build
+    lib = str(tmp_path / "libmra_sanitized.so")
+    build.build_sanitized(lib, obj_dir=str(tmp_path / "obj"))
+    env = dict(os.environ, LD_PRELOAD=build.asan_runtime(), ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    out = subprocess.run([sys.executable, "-c", _SANITIZED_DRIVER, lib], capture_output=True, text=True, env=env,
+                         timeout=600)
+    assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in out.stderr and "runtime error" not in out.stderr, out.stderr[-4000:]
+    n_ok, n_err = (int(w) for w in out.stdout.split()[1:5:3])
+    assert n_ok > 0 and n_err > 0
 
 
 def test_geometry_validation_needs_no_device(lib):
