@@ -76,6 +76,18 @@ struct Op16<kFP16> {
   }
 };
 
+// Order of the 16 x 16 matrix-core block.  Its rows are (row, p) and its
+// columns (ref, q), interleaved: block row 2 row + p, block column 2 ref + q.
+// The reference operand is packed in that column order; the particle
+// operand is stored with position p * 8 + row, which block row j reads
+// through a_block_pos(j).  Lane ln then holds column 2 ref + q = ln & 15 for the
+// rows 2 (ln / 16) and 2 (ln / 16) + 1, both p: the four entries U_pq of a
+// (row, ref) pair sit in two neighbouring lanes (q = 0, 1).
+__device__ __forceinline__ int a_block_pos(int j) { return (j & 1) * 8 + (j >> 1); }
+// The (row, ref) pair that lane ln gathers, as row * 8 + ref: row
+// 2 (ln / 16) + q, ref (ln / 2) & 7, q = ln & 1.
+__device__ __forceinline__ int lane_pair(int ln) { return (2 * (ln >> 4) + (ln & 1)) * 8 + ((ln >> 1) & 7); }
+
 // Particle operand of lane ln for slot `slot`: ring g*R4 + t of lane group
 // g = ln/16 at element t * ring_stride(LAYOUT) (kRingMajor or kSlotMajor,
 // fixed per contraction form; the host has the resampler write the same
@@ -88,8 +100,8 @@ __device__ __forceinline__ const float* a_lane(const CorrArgs& a, int tile, int 
   static_assert(LAYOUT != kRingPerm, "the paired layout is read with a_pair");
   const int R4 = RX > 0 ? RX : a.R4;
   if constexpr (LAYOUT == kSlotMajor)
-    return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + (ln & 15);
-  return a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + slot) * 16 + (ln & 15);
+    return a.A + (size_t)(tile * kSlots + slot) * 64 * R4 + ((ln >> 4) * R4) * 16 + a_block_pos(ln & 15);
+  return a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + slot) * 16 + a_block_pos(ln & 15);
 }
 // Element t of the lane's operand: ring (ln/16)*R4 + t.  The load is never
 // conditional (a conditional load waits for its data before the next one is
@@ -127,22 +139,40 @@ __device__ __forceinline__ f32x2 a_pair(const CorrArgs& a, const float* ap, int 
 // magnitudes, the others through their summed energy.
 constexpr int kLowSlots = 32;
 
-// store a 16x16 MFMA block of slot `slot` into the LDS spectrum state
-__device__ __forceinline__ void store_block(float* st, int slot, int ln, f32x4 acc) {
-  const int p = ln >> 5, q = (ln >> 3) & 1, ref = ln & 7, row0 = ((ln >> 4) & 1) * 4;
-#pragma unroll
-  for (int i2 = 0; i2 < 4; ++i2) {
-    const int P = (row0 + i2) * 8 + ref;
-    st[((slot * 2 + p) * 64 + P) * 2 + (q ^ p)] = acc[i2];
-  }
+// swap the values of neighbouring lanes (DPP quad_perm [1, 0, 3, 2])
+__device__ __forceinline__ float swap_adjacent(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false));
 }
 
-// Add the squares of the lane's block entries, times msk (1 for a slot at or
-// above kLowSlots, else 0), to e: its four rows' share of the pairs'
-// high-slot energy.  Slot w + NW i is a high slot exactly when i >= kLowSlots / NW.
-__device__ __forceinline__ void add_energy(float (&e)[4], f32x4 acc, float msk) {
-#pragma unroll
-  for (int i2 = 0; i2 < 4; ++i2) e[i2] = fmaf(acc[i2] * msk, acc[i2], e[i2]);
+// Block of slot `slot` -> the lane's pair (lane_pair(ln) = P): the four
+// entries U_pq gathered with one exchange between the two lanes of the
+// pair, stored as the state halves (U00, U01) and (U11, U10), and added to
+// the pair's pruning bound: a slot below kLowSlots (low) with the exact
+// magnitudes of its two spectrum values per mirror, a slot above through
+// its energy, the sum of the squares.
+__device__ __forceinline__ void pair_block(float2* stc, int slot, int ln, int P, f32x4 acc, bool low, float& b0,
+                                           float& b1, float& en) {
+  const bool q = ln & 1;
+  // lane q = 0 holds (row 2g: U00, U10; row 2g + 1: U00, U10), lane q = 1
+  // the same rows' U01, U11; each sends the entries of the other's row
+  const float r0 = swap_adjacent(q ? acc[0] : acc[2]), r1 = swap_adjacent(q ? acc[1] : acc[3]);
+  const float u00 = q ? r0 : acc[0], u01 = q ? acc[2] : r0;
+  const float u10 = q ? r1 : acc[1], u11 = q ? acc[3] : r1;
+  stc[(slot * 2) * 64 + P] = make_float2(u00, u01);
+  stc[(slot * 2 + 1) * 64 + P] = make_float2(u11, u10);
+  const float s1 = u00 + u11, d1 = u00 - u11, s2 = u01 + u10, d2 = u01 - u10;
+  if (low) {
+    if (slot == 0) {  // |g_0| + |g_128|, the same for both mirrors
+      const float g = 0.25f * (fabsf(s1 + s2) + fabsf(s1 - s2));
+      b0 += g;
+      b1 += g;
+    } else {          // 2|G_0,f| = |(s1, d2)|, 2|G_1,f| = |(s2, d1)|
+      b0 += sqrtf(s1 * s1 + d2 * d2);
+      b1 += sqrtf(s2 * s2 + d1 * d1);
+    }
+  } else {
+    en = fmaf(u00, u00, fmaf(u01, u01, fmaf(u10, u10, fmaf(u11, u11, en))));
+  }
 }
 
 // Contraction of one reference tile with FP32 operands for the wave's
@@ -157,7 +187,7 @@ struct Fp32Contract {
   static constexpr int RX = EXACT ? MAXR : 0;
   static constexpr int LAYOUT = (NW == 8 && RES) ? kRingPerm : kSlotMajor;
   float areg[RES ? SPW : 1][RES ? MAXR : 1];
-  float e[4];  // high-slot energy of the lane's entries (store_block)
+  float bound0, bound1, energy;  // the lane's pair's pruning bound terms (pair_block)
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
@@ -166,7 +196,7 @@ struct Fp32Contract {
         // (i even, i + 1) interleaved by element: one base address, constant
         // offsets, one 8-byte load for two slots
         const int R4 = RX > 0 ? RX : a.R4;
-        const float* a0 = a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + 16 * w) * 16 + 2 * (ln & 15);
+        const float* a0 = a.A + ((size_t)(tile * 4 + (ln >> 4)) * R4 * kSlots + 16 * w) * 16 + 2 * a_block_pos(ln & 15);
 #pragma unroll
         for (int i2 = 0; i2 < SPW / 2; ++i2) {
 #pragma unroll
@@ -187,9 +217,10 @@ struct Fp32Contract {
     }
   }
 
-  __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
+  __device__ __forceinline__ void run(const CorrArgs& a, float2* stc, int tile, int kt, int w, int ln) {
     const int R4 = EXACT ? MAXR : a.R4;
-    e[0] = e[1] = e[2] = e[3] = 0.f;
+    const int P = lane_pair(ln);
+    bound0 = bound1 = energy = 0.f;
     auto loadb = [&](int i, float (&dst)[MAXR]) {
       const float* bp = a.B32 + ((size_t)(kt * kSlots + w + NW * i) * R4) * 64 + ln;
 #pragma unroll
@@ -213,12 +244,8 @@ struct Fp32Contract {
         }
         if (i + 2 < SPW) loadb(i + 2, b[(i + 2) % 4]);
         if (i + 3 < SPW) loadb(i + 3, b[(i + 3) % 4]);
-        store_block(st, w + NW * i, ln, acc0);
-        store_block(st, w + NW * (i + 1), ln, acc1);
-        if (i >= kLowSlots / NW) {
-          add_energy(e, acc0, 1.f);
-          add_energy(e, acc1, 1.f);
-        }
+        pair_block(stc, w + NW * i, ln, P, acc0, i < kLowSlots / NW, bound0, bound1, energy);
+        pair_block(stc, w + NW * (i + 1), ln, P, acc1, i + 1 < kLowSlots / NW, bound0, bound1, energy);
       }
     } else {
       // both operands streamed, one slot ahead (explicit double buffer so
@@ -234,8 +261,7 @@ struct Fp32Contract {
 #pragma unroll
         for (int t = 0; t < MAXR; ++t)
           if (t < R4) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x[t], y[t], acc, 0, 0, 0);
-        store_block(st, slot, ln, acc);
-        add_energy(e, acc, slot >= kLowSlots ? 1.f : 0.f);
+        pair_block(stc, slot, ln, P, acc, slot < kLowSlots, bound0, bound1, energy);
       };
       loadb(0, b0);
       loada(0, a0);
@@ -281,7 +307,7 @@ struct Half16Contract {
     u32x2 t;
   };
   Frag areg[RES ? SPW : 1];
-  float e[4];  // high-slot energy of the lane's entries (store_block)
+  float bound0, bound1, energy;  // the lane's pair's pruning bound terms (pair_block)
 
   // Element t (ring (ln/16) R4 + t) of the lane's row for each t < MAXR is
   // read unconditionally: the index is clamped into the row tile's rings,
@@ -305,7 +331,7 @@ struct Half16Contract {
   // The lane's operand of slot `slot` (streamed variant): one 2-byte load
   // per element.
   __device__ __forceinline__ void fetch(const CorrArgs& a, int tile, int slot, int ln, Frag& dst, bool nt) {
-    const int idx = a16_index(slot_pos(slot), ln & 15);
+    const int idx = a16_index(slot_pos(slot), a_block_pos(ln & 15));
     uint32_t v[8 * NS];
 #pragma unroll
     for (int t = 0; t < 8 * NS; ++t) {
@@ -331,7 +357,7 @@ struct Half16Contract {
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
       static_assert(NW == 8, "the interleaved runs hold 8 slots of each of 8 waves");
-      const int k = ln & 15;
+      const int k = a_block_pos(ln & 15);
 #pragma unroll
       for (int hh = 0; hh < 2; ++hh) {
         u32x4 u[8 * NS];
@@ -358,8 +384,9 @@ struct Half16Contract {
     }
   }
 
-  __device__ __forceinline__ void run(const CorrArgs& a, float* st, int tile, int kt, int w, int ln) {
+  __device__ __forceinline__ void run(const CorrArgs& a, float2* stc, int tile, int kt, int w, int ln) {
     const int ns = EXACT ? NS : a.NS;
+    const int P = lane_pair(ln);
     const int bt = a.BT;                          // last step: bt elements per lane
     const int se = (ns - 1) * 512 + 64 * bt;      // elements per slot block
     const int h = bt / 2;                         // dwords per lane in the last step
@@ -368,7 +395,7 @@ struct Half16Contract {
     // elements t >= R4, all zero, so it adds exact zeros (every stored value
     // is finite).  With ns == 1 the last-step address is step 0's, read and
     // unused.
-    e[0] = e[1] = e[2] = e[3] = 0.f;
+    bound0 = bound1 = energy = 0.f;
     auto loadb = [&](int i, Frag& dst) {
       const uint16_t* bp = a.B16 + (size_t)(kt * kSlots + w + NW * i) * se;
       dst.f[0] = *reinterpret_cast<const u32x4*>(bp + ln * 8);  // step 0 is always 8 wide
@@ -387,7 +414,7 @@ struct Half16Contract {
         }
       }
     };
-    auto chain = [&](const Frag& x, const Frag& y, int slot) {
+    auto chain = [&](const Frag& x, const Frag& y, int slot, bool low) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NF; ++s)
@@ -399,8 +426,7 @@ struct Half16Contract {
         const u32x4 xa = {x.t[0], x.t[1], 0u, 0u}, yb = {y.t[0], y.t[1], 0u, 0u};
         if (ns == NS) acc = Op16<PREC>::mfma(__builtin_bit_cast(V, xa), __builtin_bit_cast(V, yb), acc);
       }
-      store_block(st, slot, ln, acc);
-      return acc;
+      pair_block(stc, slot, ln, P, acc, low, bound0, bound1, energy);
     };
     if constexpr (RES) {
       Frag b[2];
@@ -408,8 +434,7 @@ struct Half16Contract {
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
         if (i + 1 < SPW) loadb(i + 1, b[(i + 1) % 2]);
-        const f32x4 acc = chain(areg[RES ? i : 0], b[i % 2], w + NW * i);
-        if (i >= kLowSlots / NW) add_energy(e, acc, 1.f);
+        chain(areg[RES ? i : 0], b[i % 2], w + NW * i, i < kLowSlots / NW);
         // keep each slot's store next to its products (a schedule that
         // defers them all holds 16 blocks of results and runs slower)
         __builtin_amdgcn_sched_barrier(0);
@@ -423,12 +448,12 @@ struct Half16Contract {
       for (int i = 0; i < SPW; i += 2) {
         loadb(i + 1, b1);
         fetch(a, tile, w + NW * (i + 1), ln, x1, false);
-        add_energy(e, chain(x0, b0, w + NW * i), i >= kLowSlots / NW ? 1.f : 0.f);
+        chain(x0, b0, w + NW * i, i < kLowSlots / NW);
         if (i + 2 < SPW) {
           loadb(i + 2, b0);
           fetch(a, tile, w + NW * (i + 2), ln, x0, false);
         }
-        add_energy(e, chain(x1, b1, w + NW * (i + 1)), i + 1 >= kLowSlots / NW ? 1.f : 0.f);
+        chain(x1, b1, w + NW * (i + 1), i + 1 < kLowSlots / NW);
       }
     }
   }
@@ -440,7 +465,7 @@ struct CorrSmem {
   float2* stc;
   unsigned long long* key;  // [8] best candidate of each row so far (ordered key, 0 = none)
   float4* pp;               // [2][NW][64] per (reference-tile parity, wave, pair): low-slot bound of
-                            // both mirrors, high-slot energy of the two p halves
+                            // both mirrors, high-slot energy, unused
   int* list;                // [NW][64] each wave's list of the pairs that need the inverse FFT
   float* thr;               // [8] each row's best before this reference tile's inverse FFT
   float* pt;                // [8] best over the rows of the row's particle (this tile and carried)
@@ -467,16 +492,6 @@ struct CorrSmem {
            8 * sizeof(float) * 2 + 8 * sizeof(int) + 2 * sizeof(float) + 2 * sizeof(int) + kNphi * sizeof(float2);
   }
 };
-
-// rotate within rows of 16 lanes (DPP row_ror): lane i gets lane (i + O) mod 16's value
-template <int O>
-__device__ __forceinline__ int ror16(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x120 + O, 0xf, 0xf, false);
-}
-template <int O>
-__device__ __forceinline__ float ror16f(float v) {
-  return __int_as_float(ror16<O>(__float_as_int(v)));
-}
 
 __device__ __forceinline__ void lds_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -569,43 +584,10 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     const int par = kt & 1;  // energy and bound partials alternate, so a wave may write the next
                              // tile's while another still reads this one's
     // ---------------- contraction on the matrix cores ----------------
-    con.run(a, sm.st, tile, kt, w, ln);
-    if (prune) {
-      // high-slot energy of each pair: the lane's four rows summed with its
-      // q partner (lane ^ 8, in the same row of 16: a DPP rotation by 8);
-      // the two p halves (lane ^ 32) are stored apart and added below
-      float e[4];
-#pragma unroll
-      for (int i2 = 0; i2 < 4; ++i2) e[i2] = con.e[i2] + ror16f<8>(con.e[i2]);
-      if ((ln & 8) == 0) {
-        const int ref = ln & 7, row0 = ((ln >> 4) & 1) * 4, p = ln >> 5;
-#pragma unroll
-        for (int i2 = 0; i2 < 4; ++i2) {
-          float* q = reinterpret_cast<float*>(&sm.pp[(par * NW + w) * 64 + (row0 + i2) * 8 + ref]);
-          q[2 + p] = e[i2];
-        }
-      }
-      // exact terms of the wave's own low slots (written by this wave)
-      lds_wave_sync();
-      const int P = ln;
-      float b0 = 0.f, b1 = 0.f;
-#pragma unroll
-      for (int i = 0; i < kLowSlots / NW; ++i) {
-        const int slot = w + NW * i;
-        const float2 h0 = sm.stc[(slot * 2) * 64 + P];      // (U00, U01)
-        const float2 h1 = sm.stc[(slot * 2 + 1) * 64 + P];  // (U11, U10)
-        const float s1 = h0.x + h1.x, d1 = h0.x - h1.x, s2 = h0.y + h1.y, d2 = h0.y - h1.y;
-        if (slot == 0) {  // |g_0| + |g_128|, the same for both mirrors
-          const float g = 0.25f * (fabsf(s1 + s2) + fabsf(s1 - s2));
-          b0 += g;
-          b1 += g;
-        } else {          // 2|G_0,f| = |(s1, d2)|, 2|G_1,f| = |(s2, d1)|
-          b0 += sqrtf(s1 * s1 + d2 * d2);
-          b1 += sqrtf(s2 * s2 + d1 * d1);
-        }
-      }
-      *reinterpret_cast<float2*>(&sm.pp[(par * NW + w) * 64 + P]) = make_float2(b0, b1);
-    }
+    con.run(a, sm.stc, tile, kt, w, ln);
+    // the wave's share of each pair's bound (its slots' terms, gathered in
+    // the contraction by the pair's lanes)
+    if (prune) sm.pp[(par * NW + w) * 64 + lane_pair(ln)] = make_float4(con.bound0, con.bound1, con.energy, 0.f);
     __syncthreads();
     // each row's best before this tile's candidates arrive: candidates of this
     // tile are recorded only above it (equal values of earlier tiles have
@@ -622,7 +604,7 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
         const float4 b = sm.pp[(par * NW + w2) * 64 + P];
         B0 += b.x;
         B1 += b.y;
-        E += b.z + b.w;
+        E += b.z;
       }
       const float bound = (a.M == 2 ? fmaxf(B0, B1) : B0) + sqrtf(2.f * (kSlots - kLowSlots) * E);
       const int row_l = P >> 3, ref_l = P & 7;

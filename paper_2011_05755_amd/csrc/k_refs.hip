@@ -80,8 +80,9 @@ __global__ void k_ref_qhat(RefArgs a) {
 }
 
 __device__ __forceinline__ double packed_value(const RefArgs& a, int kt, int slot, int lane, int t) {
+  // lane = 16 g + 2 ref + q: ring group g, column (ref, q) of the contraction's block
   const int g = lane >> 4, n = lane & 15;
-  const int q = n >> 3, ref = kt * kRefTile + (n & 7);
+  const int q = n & 1, ref = kt * kRefTile + (n >> 1);
   const int ring = g * a.R4 + t;
   if (t >= a.R4 || ring >= a.R || ref >= a.K) return 0.0;
   const double2* Q = a.Qs + (size_t)ref * 129 * a.R;
