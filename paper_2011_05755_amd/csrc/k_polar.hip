@@ -40,7 +40,26 @@ __device__ __forceinline__ int group_bcast(int v) {
   return __builtin_amdgcn_ds_swizzle(v, 0x18 | (J << 5));
 }
 
-template <int MODE>
+// Operand element type written in mode 0: FP32 (kRingPerm or kSlotMajor,
+// chosen at run time), or BF16 / FP16 in kRingPerm16.
+enum PolarOut { kOutF32 = 0, kOutBF16 = 1, kOutFP16 = 2 };
+
+// Two values in the contraction's 16-bit type, each rounded to nearest
+// (even) once, packed with x in the low half.
+template <int OUT>
+__device__ __forceinline__ uint32_t pack16(float x, float y) {
+  typedef float f32x2v __attribute__((ext_vector_type(2)));
+  const f32x2v v = {x, y};
+  if constexpr (OUT == kOutBF16) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  } else {
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+  }
+}
+
+template <int MODE, int OUT>
 __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float* smem) {
   float* img = smem;
   float2* scr = reinterpret_cast<float2*>(smem + ((a.Lp * a.Lp + 3) & ~3));
@@ -72,6 +91,10 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
     // being hoisted out of the loop and kept in registers.
     int lx = l, rx = rl, lnx = ln;
     asm volatile("" : "+v"(lx), "+v"(rx), "+v"(lnx));
+    // (their ranges restated, so that products with them take the 24-bit multiplier)
+    lx &= 7;
+    rx &= 7;
+    lnx &= 63;
     int k1a, k1b;
     fwd_cols(lx, k1a, k1b);
     const int row = (q0 + grp) * 8 + rx;
@@ -189,8 +212,8 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
       const bool slot_major = a.a_layout == kSlotMajor, perm = a.a_layout == kRingPerm;
       // 16-bit operand: each value rounded once, as the contraction's matrix
       // cores take it (FP16 scaled by the particle's power of two)
-      const bool half = a.a_layout == kRingPerm16;
-      const float hscale = (half && a.prec == kFP16) ? fp16_operand_scale(a.maxabs[n]) : 1.f;
+      constexpr bool half = OUT != kOutF32;
+      const float hscale = OUT == kOutFP16 ? fp16_operand_scale(a.maxabs[n]) : 1.f;
       const int ss = slot_major ? a.R4 * 64 : 16;
       float* dst = a.out + (slot_major ? (size_t)tile * kSlots * a.R4 * 64 + ring * 16
                                        : ((size_t)tile * 4 * a.R4 + ring) * kSlots * 16);
@@ -217,7 +240,7 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
           stage[sl * 16 + ((8 + rx) ^ sw)] = h ? hi_b[k] : lo_b[k];
         }
         wave_sync();
-        if (half) {
+        if constexpr (half) {
           // kRingPerm16: the staged slots 64 h + sl are positions 16 (sl % 8)
           // + 8 h + sl / 8, i.e. the runs G = 2 w + h (w = sl % 8); lane
           // (w, k) of chunk c = lane + 64 q writes element k of the 8
@@ -230,51 +253,49 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
             uint32_t u[4];
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-              uint32_t pr = 0;
-#pragma unroll
-              for (int b = 0; b < 2; ++b) {
-                const int sl = w + 8 * (2 * jj + b);
-                const float v = stage[sl * 16 + (k ^ ((sl & 3) << 2))] * hscale;
-                const uint32_t bits = a.prec == kFP16 ? __builtin_bit_cast(uint16_t, (_Float16)v)
-                                                      : __builtin_bit_cast(uint16_t, (__bf16)v);
-                pr |= bits << (16 * b);
+              const int sl0 = w + 16 * jj, sl1 = sl0 + 8;  // positions 2 jj, 2 jj + 1 of the run
+              float v0 = stage[sl0 * 16 + (k ^ ((sl0 & 3) << 2))];
+              float v1 = stage[sl1 * 16 + (k ^ ((sl1 & 3) << 2))];
+              if constexpr (OUT == kOutFP16) {
+                v0 *= hscale;
+                v1 *= hscale;
               }
-              u[jj] = pr;
+              u[jj] = pack16<OUT>(v0, v1);
             }
             if (row >= first && row < last)
               *reinterpret_cast<uint4*>(blk + a16_index(16 * w + 8 * h, k)) = make_uint4(u[0], u[1], u[2], u[3]);
           }
           wave_sync();
-          continue;
-        }
+        } else {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-          if (perm) {
-            const int s0 = 2 * it + sp, s1 = s0 + 8, sw = (s0 & 3) << 2;  // s1 & 3 == s0 & 3
-            const float2 v0 = *reinterpret_cast<const float2*>(stage + s0 * 16 + ((2 * c) ^ sw));
-            const float2 v1 = *reinterpret_cast<const float2*>(stage + s1 * 16 + ((2 * c) ^ sw));
-            float* o = pair_dst + 32 * (16 * it + 4 * h);
-            if (full_p) {
-              *reinterpret_cast<float4*>(o) = make_float4(v0.x, v1.x, v0.y, v1.y);
-            } else {
-              if (rp >= first && rp < last) { o[0] = v0.x; o[1] = v1.x; }
-              if (rp + 1 >= first && rp + 1 < last) { o[2] = v0.y; o[3] = v1.y; }
+          for (int it = 0; it < 4; ++it) {
+            if (perm) {
+              const int s0 = 2 * it + sp, s1 = s0 + 8, sw = (s0 & 3) << 2;  // s1 & 3 == s0 & 3
+              const float2 v0 = *reinterpret_cast<const float2*>(stage + s0 * 16 + ((2 * c) ^ sw));
+              const float2 v1 = *reinterpret_cast<const float2*>(stage + s1 * 16 + ((2 * c) ^ sw));
+              float* o = pair_dst + 32 * (16 * it + 4 * h);
+              if (full_p) {
+                *reinterpret_cast<float4*>(o) = make_float4(v0.x, v1.x, v0.y, v1.y);
+              } else {
+                if (rp >= first && rp < last) { o[0] = v0.x; o[1] = v1.x; }
+                if (rp + 1 >= first && rp + 1 < last) { o[2] = v0.y; o[3] = v1.y; }
+              }
+              continue;
             }
-            continue;
+            const int sl = it * 16 + (lnx >> 2);
+            const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
+            float* o = lane_dst + (size_t)(64 * h + 16 * it) * ss;
+            if (full) {
+              *reinterpret_cast<float4*>(o) = val;
+            } else {
+              if (r0 + 0 >= first && r0 + 0 < last) o[0] = val.x;
+              if (r0 + 1 >= first && r0 + 1 < last) o[1] = val.y;
+              if (r0 + 2 >= first && r0 + 2 < last) o[2] = val.z;
+              if (r0 + 3 >= first && r0 + 3 < last) o[3] = val.w;
+            }
           }
-          const int sl = it * 16 + (lnx >> 2);
-          const float4 val = *reinterpret_cast<const float4*>(stage + sl * 16 + ((part ^ (sl & 3)) << 2));
-          float* o = lane_dst + (size_t)(64 * h + 16 * it) * ss;
-          if (full) {
-            *reinterpret_cast<float4*>(o) = val;
-          } else {
-            if (r0 + 0 >= first && r0 + 0 < last) o[0] = val.x;
-            if (r0 + 1 >= first && r0 + 1 < last) o[1] = val.y;
-            if (r0 + 2 >= first && r0 + 2 < last) o[2] = val.z;
-            if (r0 + 3 >= first && r0 + 3 < last) o[3] = val.w;
-          }
+          wave_sync();
         }
-        wave_sync();
       }
     } else {  // MODE 2: plain spectra
       float* o = a.out + (((size_t)n * a.S + (valid ? s : 0)) * a.R + ring) * 129 * 2;
@@ -293,21 +314,27 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
   }
 }
 
-template <int MODE>
+template <int MODE, int OUT>
 __global__ __launch_bounds__(kPolarThreads) void k_polar_fft(PolarArgs a) {
   extern __shared__ float smem[];
   const int n = xcd_item();
   if (n >= a.n_part) return;
-  polar_particle<MODE>(a, n, smem);
+  polar_particle<MODE, OUT>(a, n, smem);
 }
 
+// every piece of a batch writes the same operand type
+template <int OUT>
 __global__ __launch_bounds__(kPolarThreads) void k_polar_batch(PolarBatch b) {
   extern __shared__ float smem[];
   const int item = xcd_item();
   if (item >= b.start[b.n]) return;
   int p = 0;
   while (p + 1 < b.n && b.start[p + 1] <= item) ++p;
-  polar_particle<0>(b.piece[p], item - b.start[p], smem);
+  polar_particle<0, OUT>(b.piece[p], item - b.start[p], smem);
+}
+
+static int polar_out(const PolarArgs& a) {
+  return a.a_layout != kRingPerm16 ? kOutF32 : (a.prec == kFP16 ? kOutFP16 : kOutBF16);
 }
 
 size_t polar_lds_bytes(int Lp) {
@@ -318,8 +345,18 @@ size_t polar_lds_bytes(int Lp) {
 hipError_t launch_polar_batch(const PolarBatch& b, hipStream_t st) {
   if (b.n <= 0 || b.start[b.n] <= 0) return hipSuccess;
   int lp = 0;
-  for (int i = 0; i < b.n; ++i) lp = b.piece[i].Lp > lp ? b.piece[i].Lp : lp;
-  hipLaunchKernelGGL(k_polar_batch, dim3((b.start[b.n] + 7) / 8 * 8), dim3(kPolarThreads), polar_lds_bytes(lp), st, b);
+  const int out = polar_out(b.piece[0]);
+  for (int i = 0; i < b.n; ++i) {
+    lp = b.piece[i].Lp > lp ? b.piece[i].Lp : lp;
+    if (polar_out(b.piece[i]) != out) return hipErrorInvalidValue;
+  }
+  const dim3 grid((b.start[b.n] + 7) / 8 * 8), block(kPolarThreads);
+  const size_t lds = polar_lds_bytes(lp);
+  switch (out) {
+    case kOutF32: hipLaunchKernelGGL(k_polar_batch<kOutF32>, grid, block, lds, st, b); break;
+    case kOutBF16: hipLaunchKernelGGL(k_polar_batch<kOutBF16>, grid, block, lds, st, b); break;
+    default: hipLaunchKernelGGL(k_polar_batch<kOutFP16>, grid, block, lds, st, b); break;
+  }
   return hipGetLastError();
 }
 
@@ -328,9 +365,15 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
   const size_t lds = polar_lds_bytes(a.Lp);
   dim3 grid((a.n_part + 7) / 8 * 8), block(kPolarThreads);
   switch (mode) {
-    case 0: hipLaunchKernelGGL(k_polar_fft<0>, grid, block, lds, st, a); break;
-    case 1: hipLaunchKernelGGL(k_polar_fft<1>, grid, block, lds, st, a); break;
-    default: hipLaunchKernelGGL(k_polar_fft<2>, grid, block, lds, st, a); break;
+    case 0:
+      switch (polar_out(a)) {
+        case kOutF32: hipLaunchKernelGGL((k_polar_fft<0, kOutF32>), grid, block, lds, st, a); break;
+        case kOutBF16: hipLaunchKernelGGL((k_polar_fft<0, kOutBF16>), grid, block, lds, st, a); break;
+        default: hipLaunchKernelGGL((k_polar_fft<0, kOutFP16>), grid, block, lds, st, a); break;
+      }
+      break;
+    case 1: hipLaunchKernelGGL((k_polar_fft<1, kOutF32>), grid, block, lds, st, a); break;
+    default: hipLaunchKernelGGL((k_polar_fft<2, kOutF32>), grid, block, lds, st, a); break;
   }
   return hipGetLastError();
 }
