@@ -46,13 +46,6 @@ __device__ __forceinline__ float2 w256c(const float2* cs, int e) {
   return make_float2(c.x, -c.y);
 }
 
-// logical index j (0..255) of a pair's spectrum -> float2 index in LDS state
-__device__ __forceinline__ int vidx(int j, int P) {
-  const int slot = j < 128 ? j : ((256 - j) & 127);
-  const int half = j < 128 ? 0 : 1;
-  return (slot * 2 + half) * 64 + P;
-}
-
 __device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
