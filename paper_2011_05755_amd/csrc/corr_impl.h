@@ -182,6 +182,18 @@ struct Fp32Contract {
   float areg[RES ? SPW : 1][RES ? MAXR : 1];
   float bound0, bound1, energy;  // the lane's pair's pruning bound terms (pair_block)
 
+  // the lane's reference operand of slot `slot` in reference tile kt
+  __device__ __forceinline__ void load_b(const CorrArgs& a, int kt, int slot, int ln, float (&dst)[MAXR]) const {
+    const int R4 = EXACT ? MAXR : a.R4;
+    const float* bp = a.B32 + ((size_t)(kt * kSlots + slot) * R4) * 64 + ln;
+#pragma unroll
+    for (int t = 0; t < MAXR; ++t) dst[t] = bp[(t < R4 ? t : R4 - 1) * 64];  // unconditional
+  }
+  // No operand is loaded ahead across the inverse FFT: the registers it
+  // would hold there are the resident operand's (spills cost more than the
+  // latency it hides).
+  __device__ __forceinline__ void prefetch(const CorrArgs&, int, int, int) {}
+
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
       if constexpr (LAYOUT == kRingPerm) {
@@ -214,11 +226,7 @@ struct Fp32Contract {
     const int R4 = EXACT ? MAXR : a.R4;
     const int P = lane_pair(ln);
     bound0 = bound1 = energy = 0.f;
-    auto loadb = [&](int i, float (&dst)[MAXR]) {
-      const float* bp = a.B32 + ((size_t)(kt * kSlots + w + NW * i) * R4) * 64 + ln;
-#pragma unroll
-      for (int t = 0; t < MAXR; ++t) dst[t] = bp[(t < R4 ? t : R4 - 1) * 64];  // unconditional
-    };
+    auto loadb = [&](int i, float (&dst)[MAXR]) { load_b(a, kt, w + NW * i, ln, dst); };
     if constexpr (RES) {
       // slots in pairs: two independent accumulation chains keep the matrix
       // pipe busy; the reference operand of the next pair is in flight
@@ -301,6 +309,7 @@ struct Half16Contract {
   };
   Frag areg[RES ? SPW : 1];
   float bound0, bound1, energy;  // the lane's pair's pruning bound terms (pair_block)
+  Frag bpre;                     // RES: reference operand of the wave's first slot, loaded ahead
 
   // Element t (ring (ln/16) R4 + t) of the lane's row for each t < MAXR is
   // read unconditionally: the index is clamped into the row tile's rings,
@@ -377,36 +386,44 @@ struct Half16Contract {
     }
   }
 
-  __device__ __forceinline__ void run(const CorrArgs& a, float2* stc, int tile, int kt, int w, int ln) {
+  // the lane's reference operand of slot `slot` in reference tile kt.  Last-step
+  // dword j of the lane is read at index min(j, h - 1): a dword j >= h
+  // repeats stored values, which meet the particle operand's elements t >=
+  // R4, all zero, so it adds exact zeros (every stored value is finite).
+  // With ns == 1 the last-step address is step 0's, read and unused.
+  __device__ __forceinline__ void load_b(const CorrArgs& a, int kt, int slot, int ln, Frag& dst) const {
     const int ns = EXACT ? NS : a.NS;
-    const int P = lane_pair(ln);
     const int bt = a.BT;                          // last step: bt elements per lane
     const int se = (ns - 1) * 512 + 64 * bt;      // elements per slot block
     const int h = bt / 2;                         // dwords per lane in the last step
-    // Last-step dword j of the lane is read at index min(j, h - 1): a dword
-    // j >= h repeats stored values, which meet the particle operand's
-    // elements t >= R4, all zero, so it adds exact zeros (every stored value
-    // is finite).  With ns == 1 the last-step address is step 0's, read and
-    // unused.
-    bound0 = bound1 = energy = 0.f;
-    auto loadb = [&](int i, Frag& dst) {
-      const uint16_t* bp = a.B16 + (size_t)(kt * kSlots + w + NW * i) * se;
-      dst.f[0] = *reinterpret_cast<const u32x4*>(bp + ln * 8);  // step 0 is always 8 wide
-      if constexpr (NS == 2) {
-        const uint32_t* tp = reinterpret_cast<const uint32_t*>(bp + (ns - 1) * 512 + ln * bt);
-        if constexpr (NARROW) {
+    const uint16_t* bp = a.B16 + (size_t)(kt * kSlots + slot) * se;
+    dst.f[0] = *reinterpret_cast<const u32x4*>(bp + ln * 8);  // step 0 is always 8 wide
+    if constexpr (NS == 2) {
+      const uint32_t* tp = reinterpret_cast<const uint32_t*>(bp + (ns - 1) * 512 + ln * bt);
+      if constexpr (NARROW) {
 #pragma unroll
-          for (int j = 0; j < 2; ++j) dst.t[j] = tp[j < h ? j : h - 1];
-        } else if constexpr (EXACT) {
-          dst.f[1] = *reinterpret_cast<const u32x4*>(tp);  // 8 wide: one 16-byte load
-        } else {
-          // (four 4-byte loads cost the address path four times one 16-byte
-          // load: batched launches keep the ring buckets apart to avoid this)
+        for (int j = 0; j < 2; ++j) dst.t[j] = tp[j < h ? j : h - 1];
+      } else if constexpr (EXACT) {
+        dst.f[1] = *reinterpret_cast<const u32x4*>(tp);  // 8 wide: one 16-byte load
+      } else {
+        // (four 4-byte loads cost the address path four times one 16-byte
+        // load: batched launches keep the ring buckets apart to avoid this)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) dst.f[1][j] = tp[j < h ? j : h - 1];
-        }
+        for (int j = 0; j < 4; ++j) dst.f[1][j] = tp[j < h ? j : h - 1];
       }
-    };
+    }
+  }
+  // RES: start loading the first slot of reference tile kt, which the next
+  // run() uses (its latency then passes during the inverse FFT)
+  __device__ __forceinline__ void prefetch(const CorrArgs& a, int kt, int w, int ln) {
+    if constexpr (RES) load_b(a, kt, w, ln, bpre);
+  }
+
+  __device__ __forceinline__ void run(const CorrArgs& a, float2* stc, int tile, int kt, int w, int ln) {
+    const int ns = EXACT ? NS : a.NS;
+    const int P = lane_pair(ln);
+    bound0 = bound1 = energy = 0.f;
+    auto loadb = [&](int i, Frag& dst) { load_b(a, kt, w + NW * i, ln, dst); };
     auto chain = [&](const Frag& x, const Frag& y, int slot, bool low) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -423,7 +440,7 @@ struct Half16Contract {
     };
     if constexpr (RES) {
       Frag b[2];
-      loadb(0, b[0]);
+      b[0] = bpre;
 #pragma unroll
       for (int i = 0; i < SPW; ++i) {
         if (i + 1 < SPW) loadb(i + 1, b[(i + 1) % 2]);
@@ -578,6 +595,9 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
                              // tile's while another still reads this one's
     // ---------------- contraction on the matrix cores ----------------
     con.run(a, sm.stc, tile, kt, w, ln);
+    // the next reference tile's first operand (tile 0 again after the last:
+    // the run's next row tile starts there)
+    con.prefetch(a, kt + 1 < a.n_ref_tiles ? kt + 1 : 0, w, ln);
     // the wave's share of each pair's bound (its slots' terms, gathered in
     // the contraction by the pair's lanes)
     if (prune) sm.pp[(par * NW + w) * 64 + lane_pair(ln)] = make_float4(con.bound0, con.bound1, con.energy, 0.f);
@@ -815,6 +835,7 @@ __device__ __forceinline__ void corr_run(const CorrArgs& a, int run, const CorrS
   const int t1 = min(t0 + a.tiles_per_run, a.n_row_tiles);
   if (threadIdx.x == 0) *sm.carry_p = -1;
   lds_wave_sync();
+  con.prefetch(a, 0, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), threadIdx.x & 63);
   for (int t = t0; t < t1; ++t) corr_tile<PREC, NW, Contract, MODE, SPLIT>(a, t, sm, con);
 }
 
