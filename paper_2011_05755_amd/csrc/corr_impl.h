@@ -610,7 +610,10 @@ __device__ __forceinline__ void corr_tile(const CorrArgs& a, int tile, const Cor
     // ---------------- which pairs need the inverse FFT ----------------
     uint64_t live = ~0ull;
     if (prune) {
-      const int P = ln;
+      // (the lane index made opaque again, so that the addresses below are
+      // computed here rather than kept live across the contraction)
+      int P = ln;
+      asm volatile("" : "+v"(P));
       float B0 = 0.f, B1 = 0.f, E = 0.f;
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) {

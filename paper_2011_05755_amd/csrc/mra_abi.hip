@@ -631,14 +631,16 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
 void run_batch(mra_ctx* c, const mra_stack* stacks, int n, const std::vector<Plan>& plans) {
   const uint64_t budget = c->cap / 2;
   // stacks that share a correlation instantiation (precision, tile variant,
-  // and for the 16-bit forms the ring bucket: launches that mix buckets take
-  // the kernel's slower run-time form) are packed into the same waves;
+  // and the ring bucket: for the 16-bit forms R4 <= 8, 9..12 or 13..16, for
+  // the FP32 resident 8-wave variant the exact R4; launches that mix them
+  // take the kernel's slower run-time form) are packed into the same waves;
   // within a group the caller's order holds
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   auto group = [](const Refset& rs) {
-    const int bucket = rs.g.precision == kFP32 ? 0 : (rs.R4 <= 8 ? 0 : (rs.R4 <= 12 ? 1 : 2));
-    return (rs.g.precision * 16 + rs.variant) * 4 + bucket;
+    const int bucket = rs.g.precision == kFP32 ? (rs.variant == 0 ? rs.R4 : 0)
+                                               : (rs.R4 <= 8 ? 0 : (rs.R4 <= 12 ? 1 : 2));
+    return (rs.g.precision * 16 + rs.variant) * 32 + bucket;
   };
   auto key = [&](int i) {
     if (stacks[i].N <= 0) return 0;
