@@ -132,9 +132,10 @@ __device__ __forceinline__ f32x2 a_pair(const CorrArgs& a, const float* ap, int 
 // magnitudes, the others through their summed energy.
 constexpr int kLowSlots = 32;
 
-// swap the values of neighbouring lanes (DPP quad_perm [1, 0, 3, 2])
+// swap the values of neighbouring lanes (DPP quad_perm [1, 0, 3, 2]; every
+// lane is enabled, so no old value is needed)
 __device__ __forceinline__ float swap_adjacent(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, false));
 }
 
 // Block of slot `slot` -> the lane's pair (lane_pair(ln) = P): the four
