@@ -190,10 +190,15 @@ struct Fp32Contract {
 #pragma unroll
     for (int t = 0; t < MAXR; ++t) dst[t] = bp[(t < R4 ? t : R4 - 1) * 64];  // unconditional
   }
-  // No operand is loaded ahead across the inverse FFT: the registers it
-  // would hold there are the resident operand's (spills cost more than the
-  // latency it hides).
-  __device__ __forceinline__ void prefetch(const CorrArgs&, int, int, int) {}
+  // PRE (8 waves, resident operand, ring count exact): the reference
+  // operand of the wave's first slot of reference tile kt is loaded before
+  // the inverse FFT of the previous tile, so its latency passes under it
+  // (one slot: the registers of two would spill in these forms)
+  static constexpr bool PRE = RES && NW == 8 && EXACT;
+  float bpre[PRE ? MAXR : 1];
+  __device__ __forceinline__ void prefetch(const CorrArgs& a, int kt, int w, int ln) {
+    if constexpr (PRE) load_b(a, kt, w, ln, bpre);
+  }
 
   __device__ __forceinline__ void load_a(const CorrArgs& a, int tile, int w, int ln) {
     if constexpr (RES) {
@@ -232,7 +237,12 @@ struct Fp32Contract {
       // slots in pairs: two independent accumulation chains keep the matrix
       // pipe busy; the reference operand of the next pair is in flight
       float b[4][MAXR];
-      loadb(0, b[0]);
+      if constexpr (PRE) {
+#pragma unroll
+        for (int t = 0; t < MAXR; ++t) b[0][t] = bpre[t];
+      } else {
+        loadb(0, b[0]);
+      }
       loadb(1, b[1]);
 #pragma unroll
       for (int i = 0; i < SPW; i += 2) {
