@@ -4,9 +4,9 @@
 //   nu_k       weighted ring norm sqrt(sum_r w_r sum_j q^2),
 //   Q_k[r][f]  per-ring DFT (direct sum), times w_r / (nu_k * 256),
 // then packed into the operand layouts of the correlation kernel:
-//   FP32  [ref tile][slot][t < R4][64], lane = g*16 + q*8 + ref%8, ring = g*R4 + t
-//   16-bit [ref tile][slot][s < NS - 1][64][8], ring = g*R4 + 8 s + e, then
-//          the last step [64][BT] (BT = 2, 4 or 8: as wide as its rings need)
+//   FP32  [ref tile][slot][t < R4][64], lane = g*16 + 2*(ref%8) + q, ring = g*R4 + t
+//   16-bit [ref tile][slot][s < NS - 1][64][8] (the same lanes), ring = g*R4 + 8 s + e,
+//          then the last step [64][BT] (BT = 2, 4 or 8: as wide as its rings need)
 // with q = 0 -> c - d and q = 1 -> c + d for c + id = Q_f (slot f = 1..127)
 // and c = Q_0, d = Q_128 in slot 0; with one reference also
 //   single [ring][slot] (c - d, c + d) for the fused single-reference kernel.
