@@ -86,16 +86,17 @@ __device__ __forceinline__ void polar_particle(const PolarArgs& a, int n, float*
   const int it0 = w * per_wave, it1 = min(n_items, it0 + per_wave);
   for (int item = it0; item < it1; ++item) {
     const int ring = item / ngrp, grp = item - ring * ngrp;
-    // FP32 operand: the lane indices are made opaque here, so that the LDS
-    // and twiddle addresses derived from them are recomputed in every item
-    // instead of being hoisted out of the loop and kept in registers (kept,
-    // they take the kernel past 128 registers and two workgroups per CU);
-    // the 16-bit instances keep them (about 20 % fewer vector instructions).
-    int lx = l, rx = rl, lnx = ln;
+    // FP32 operand: the shift and lane indices are made opaque here, so that
+    // the addresses derived from them are recomputed in every item instead
+    // of being hoisted out of the loop and kept in registers (kept, with
+    // those of the lane group's index lx, they take the kernel past 128
+    // registers and two workgroups per CU); the 16-bit instances keep them
+    // all (about 20 % fewer vector instructions).
+    const int lx = l;
+    int rx = rl, lnx = ln;
     if constexpr (OUT == kOutF32) {
-      asm volatile("" : "+v"(lx), "+v"(rx), "+v"(lnx));
+      asm volatile("" : "+v"(rx), "+v"(lnx));
       // (their ranges restated, so that products with them take the 24-bit multiplier)
-      lx &= 7;
       rx &= 7;
       lnx &= 63;
     }
