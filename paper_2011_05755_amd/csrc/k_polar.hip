@@ -390,7 +390,7 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
 // candidates are the winners of the particle's a.rows best rows of the 16-bit
 // pass and their neighbours one angle step either side; the best FP32 value
 // wins (ties: the smallest flat index) and replaces the parameters.  Rows
-// whose 16-bit best lies more than kRerankMargin of the particle's 16-bit
+// whose 16-bit best lies more than a.margin of the particle's 16-bit
 // best below it are left out (they cannot win at 16-bit accuracy).
 constexpr int kMaxRescoreRows = 8;
 constexpr int kMaxRows = 289;  // shifts per particle at the largest search range (+-8)
@@ -491,7 +491,7 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
     }
     // only rows within the re-ranking margin of the particle's best (bv[0])
     // are candidates; pruning keeps their bests exact
-    const float lim = bv[0] > -INFINITY ? bv[0] - kRerankMargin * fabsf(bv[0]) : bv[0];
+    const float lim = bv[0] > -INFINITY ? bv[0] - a.margin * fabsf(bv[0]) : bv[0];
     for (int t = 0; t < kMaxRescoreRows; ++t) cand[t] = (t < nr && bv[t] >= lim) ? bi[t] : 0x7fffffff;
   }
   __syncthreads();

@@ -415,7 +415,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
   ca.table = table;
   ca.prune = rs.prune;
   ca.tiles_per_run = table ? 1 : (rs.run_tiles > 0 ? rs.run_tiles : corr_tiles_per_run(tiles, c->n_cu));
-  ca.margin = (rs.g.precision != kFP32 && rs.g.rescore_rows >= 2) ? kRerankMargin : 0.f;
+  ca.margin = rs.g.rescore_rows >= 2 ? rerank_margin(rs.g.precision) : 0.f;
   timed(c, "corr", [&] { hip_check(c, launch_corr(rs.g.precision, rs.variant, table != nullptr, ca, st), "corr"); });
   if (table) return;
 
@@ -443,6 +443,7 @@ void run_chunk(mra_ctx* c, const Refset& rs, const Plan& p, const float* parts, 
     ra.psi = out->psi; ra.mirror = out->mirror;
     ra.cc = out->cc;
     ra.rows = rs.g.rescore_rows;
+    ra.margin = rerank_margin(rs.g.precision);
     ra.S1 = p.S1; ra.S = p.S; ra.M = p.M;
     ra.row_cc = rcc; ra.row_idx = ridx;
     ra.ref_w = out->ref; ra.shift_x_w = out->shift_x; ra.shift_y_w = out->shift_y;
@@ -593,7 +594,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     ca.maxabs = mx; ca.b_scale = rs.b_scale; ca.cs32 = c->cs32;
     ca.row_cc = rcc + pc.row0; ca.row_idx = ridx + pc.row0; ca.table = nullptr; ca.prune = rs.prune;
     ca.tiles_per_run = rs.run_tiles > 0 ? rs.run_tiles : corr_tiles_per_run(ptiles, c->n_cu);
-    ca.margin = (prec != kFP32 && rs.g.rescore_rows >= 2) ? kRerankMargin : 0.f;
+    ca.margin = rs.g.rescore_rows >= 2 ? rerank_margin(prec) : 0.f;
     cb.run_start[i] = run;
 
     MergeArgs& ma = mb.piece[i];
@@ -609,7 +610,7 @@ void launch_wave(mra_ctx* c, const mra_stack* stacks, std::vector<Piece>& w) {
     ra.K = rs.K; ra.T = pc.p.T; ra.stencil = rs.stencil; ra.qhat = rs.qhat;
     ra.ref = sk.out.ref; ra.shift_x = sk.out.shift_x; ra.shift_y = sk.out.shift_y; ra.psi = sk.out.psi;
     ra.mirror = sk.out.mirror; ra.cc = sk.out.cc;
-    ra.rows = rs.g.rescore_rows; ra.S1 = pc.p.S1; ra.S = pc.p.S; ra.M = pc.p.M;
+    ra.rows = rs.g.rescore_rows; ra.margin = rerank_margin(prec); ra.S1 = pc.p.S1; ra.S = pc.p.S; ra.M = pc.p.M;
     ra.row_cc = rcc + pc.row0; ra.row_idx = ridx + pc.row0;
     ra.ref_w = sk.out.ref; ra.shift_x_w = sk.out.shift_x; ra.shift_y_w = sk.out.shift_y;
     ra.psi_w = sk.out.psi; ra.mirror_w = sk.out.mirror; ra.flat_w = sk.out.flat_index;

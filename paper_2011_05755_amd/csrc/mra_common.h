@@ -19,12 +19,16 @@ constexpr int kMaxBatchPieces = 12; // stack pieces per batched launch (kernel-a
 constexpr int kAvgChunk = 32;       // particles per partial class sum
 constexpr int kAvgThreads = 256;
 constexpr int kMaxRunTiles = 8;     // consecutive row tiles per correlation workgroup (a run)
-// Re-ranked 16-bit forms: the rows whose 16-bit best lies within this
-// fraction of the particle's best are the re-ranking candidates (and keep
-// their exact best under pruning).
-constexpr float kRerankMargin = 1.f / 128.f;
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
+
+// Re-ranked 16-bit forms: the rows whose 16-bit best lies within this
+// fraction of the particle's best are the re-ranking candidates (and keep
+// their exact best under pruning): one unit roundoff of the contraction's
+// operand type, 2^-8 for BF16 and 2^-11 for FP16.
+__host__ __device__ constexpr float rerank_margin(int prec) {
+  return prec == kBF16 ? 1.f / 256.f : (prec == kFP16 ? 1.f / 2048.f : 0.f);
+}
 
 // Layouts of the particle operand A (per row tile of 8 rows, 16 floats per
 // (ring, slot): p*8 + row%8):
@@ -157,6 +161,7 @@ struct RescoreArgs {
   // the 16-bit pass and their neighbours within +-1 angle are re-scored in
   // FP32 and the best of them becomes the result.  rows <= 1: the winner only.
   int rows, S1, S, M;
+  float margin;          // rows within this fraction of the particle's 16-bit best are candidates
   const float* row_cc;   // [n_part][S] of the 16-bit pass
   const int* row_idx;
   int32_t *ref_w, *shift_x_w, *shift_y_w, *psi_w, *mirror_w, *flat_w;  // re-ranked outputs
