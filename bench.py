@@ -151,7 +151,9 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reads and writes MIB MiB), "
                          "a reference for hardware traffic counters")
-    ap.add_argument("--workspace-gib", type=int, default=32, help="library workspace cap (chunk size)")
+    ap.add_argument("--workspace-gib", type=int, default=128,
+                    help="library workspace cap (chunk size); 128 GiB of the GPU's 288 GB: a 100k pass in 3 FP32 / "
+                         "2 16-bit chunks")
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests of the 20/s serving leg (0: no serving legs)")
     ap.add_argument("--serve-sustained", type=int, default=16, help="requests of the sustainable-rate leg")
@@ -373,6 +375,7 @@ def main() -> int:
         "config": {"workload": f"mra_c1: N={N} L={L} K={K} shifts +-{T} (S={S}) mirror rings "
                                f"{r_min}..{r_max} x 256 angles, SNR {w['snr']}, blob references, seed {w['seed']}",
                    "step": "mra_align + mra_update_averages, references resident",
+                   "workspace_gib": args.workspace_gib,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
