@@ -37,7 +37,7 @@ import time
 from typing import Callable, Iterable
 
 DEFAULT_CHUNKS = (0, 128, 512, 2048)
-DEFAULT_RUNS = (0, 1, 2, 4, 8)
+DEFAULT_RUNS = (0, 1, 2, 4, 8, 16, 32, 48)
 MAX_VARIANT = 4   # variant ids are probed from 0 up to this bound
 
 

@@ -18,7 +18,7 @@ constexpr int kPolarThreads = 64 * kPolarWaves;
 constexpr int kMaxBatchPieces = 12; // stack pieces per batched launch (kernel-argument table)
 constexpr int kAvgChunk = 32;       // particles per partial class sum
 constexpr int kAvgThreads = 256;
-constexpr int kMaxRunTiles = 8;     // consecutive row tiles per correlation workgroup (a run)
+constexpr int kMaxRunTiles = 48;    // consecutive row tiles per correlation workgroup (a run), at most
 
 enum Prec { kFP32 = 0, kBF16 = 1, kFP16 = 2 };
 
@@ -208,10 +208,15 @@ hipError_t launch_corr(int prec, int variant, bool table, const CorrArgs& a, hip
 hipError_t launch_corr_runner_up(int prec, const CorrArgs& a, hipStream_t st);
 hipError_t launch_corr_batch(int prec, int variant, const CorrBatch& b, int grid, hipStream_t st);
 // row tiles per correlation run for a launch of `tiles` tiles on n_cu CUs:
-// long runs carry each particle's best across its tiles, enough runs keep
-// every CU busy
+// long runs carry each particle's best across its tiles (fewer tiles start
+// without a threshold), enough runs keep every CU busy to the launch's end.
+// Runs of up to 8 tiles as long as every CU gets 3 runs; longer ones (up to
+// kMaxRunTiles) while every CU still gets 20, which measured best on the
+// 100k workload at 32 and 128 GiB workspaces.
 inline int corr_tiles_per_run(int tiles, int n_cu) {
-  const int g = tiles / (3 * (n_cu > 0 ? n_cu : 1));
+  const int cu = n_cu > 0 ? n_cu : 1;
+  const int a = tiles / (3 * cu), b = tiles / (20 * cu);
+  const int g = b > (a < 8 ? a : 8) ? b : (a < 8 ? a : 8);
   return g < 1 ? 1 : (g > kMaxRunTiles ? kMaxRunTiles : g);
 }
 bool corr_variant_ok(int prec, int variant, int R4);

@@ -54,7 +54,7 @@ def test_tune_picks_the_fastest_applies_it_and_caches(tmp_path):
     cost = {(0, 0): 5.0, (0, 128): 4.0, (0, 512): 4.5, (2, 0): 3.0, (2, 128): 3.5, (2, 512): 3.0}
     seen = []
 
-    run_cost = {1: 3.2, 2: 2.5, 4: 2.5, 8: 2.9}     # run 0 (the library's choice) costs cost[...]
+    run_cost = {1: 3.2, 2: 2.5, 4: 2.5, 8: 2.9, 16: 3.0, 32: 3.1, 48: 3.3}  # run 0 (the library's choice) costs cost[...]
 
     def timer(c, rid, parts, reps):
         r = c.run[rid]
@@ -74,7 +74,8 @@ def test_tune_picks_the_fastest_applies_it_and_caches(tmp_path):
     data = json.loads((tmp_path / "t.json").read_text())
     assert data["L96-R46-K64-T2-fp32"]["candidates"]["0/128"] == 4.0
 
-    assert data["L96-R46-K64-T2-fp32"]["runs"] == {"0": 3.0, "1": 3.2, "2": 2.5, "4": 2.5, "8": 2.9}
+    assert data["L96-R46-K64-T2-fp32"]["runs"] == {"0": 3.0, "1": 3.2, "2": 2.5, "4": 2.5, "8": 2.9, "16": 3.0,
+                                                   "32": 3.1, "48": 3.3}
 
     ctx2 = FakeCtx()
     ctx2.set_tuning(3, corr_variant=0)
