@@ -271,7 +271,8 @@ int mra_align_batch(mra_ctx* ctx, const mra_stack* stacks, int32_t n);
  *  run_tiles     consecutive 8-row tiles one correlation workgroup takes in
  *                order, carrying each particle's best from one tile to the
  *                next (longer runs prune more, shorter ones balance the
- *                launch better); 0: chosen from the launch size (at most 8),
+ *                launch better); 0: chosen from the launch size (up to 8
+ *                while every CU gets 3 runs, up to 48 while it gets 20),
  *                else 1..64.
  * Results do not depend on the tuning (bit for bit). */
 typedef struct mra_tuning {
