@@ -323,7 +323,7 @@ def main() -> int:
         r_host = refs.cpu().numpy()
         t0 = time.perf_counter()
         qh, _ = oracle.reference_polar(r_host, g)
-        oracle.rolled_reference_matrix(qh, g)
+        bmat = oracle.rolled_reference_matrix(qh, g)
         t_prep = time.perf_counter() - t0
         t0 = time.perf_counter()
         want = oracle.align(p_host, r_host, g)
@@ -346,6 +346,15 @@ def main() -> int:
                           f"like mra_load_refs on the GPU)",
                    host=dict(cpu_model=cpu_model, affinity_cpus=len(os.sched_getaffinity(0)),
                              blas_threads=int(threads)))
+        # (untimed) each sampled particle's gap from its best pose (reference,
+        # mirror, shift) to the best of every other pose, from the oracle's
+        # CC table: the 16-bit forms' decisions are checked where it is large
+        pose_gap = np.empty(ns)
+        for lo in range(0, ns, 8):
+            tab = oracle.cc_table(p_host[lo:lo + 8], None, g, qhat=qh, bmat=bmat)
+            per_pose = tab.reshape(tab.shape[0], -1, tab.shape[-1]).max(axis=2)
+            top2 = np.sort(per_pose, axis=1)[:, -2:]
+            pose_gap[lo:lo + tab.shape[0]] = top2[:, 1] - top2[:, 0]
         parity = {}
         for form, r in results.items():
             got = {k: v[:ns] for k, v in r["out"].items()}
@@ -355,8 +364,16 @@ def main() -> int:
             same = np.ones(ns, bool)
             for key in ("ref", "shift_x", "shift_y", "mirror", "psi"):
                 same &= got[key] == want[key]
+            pose_decided = pose_gap >= tol * np.abs(want["cc"])
+            same_pose = np.ones(ns, bool)
+            for key in ("ref", "shift_x", "shift_y", "mirror"):
+                same_pose &= got[key] == want[key]
+            dpsi = np.abs(((got["psi"] - want["psi"]) + 128) % 256 - 128)
+            same_pose &= dpsi <= 1
             parity[form] = dict(sample=ns, max_rel_cc_err=float(rel.max()), argmax_agree=int(same.sum()),
-                                decided=int(decided.sum()), decided_mismatch=int((decided & ~same).sum()))
+                                decided=int(decided.sum()), decided_mismatch=int((decided & ~same).sum()),
+                                pose_decided=int(pose_decided.sum()),
+                                pose_mismatch=int((pose_decided & ~same_pose).sum()))
         log(f"parity sample: {parity}")
 
     line = {
