@@ -394,6 +394,7 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
 // best below it are left out (they cannot win at 16-bit accuracy).
 constexpr int kMaxRescoreRows = 8;
 constexpr int kMaxRows = 289;  // shifts per particle at the largest search range (+-8)
+constexpr int kRescoreRed = 48;  // reduction slots: 4 waves x 3 lags x up to 4 candidates
 
 // FP32 CC of (ref k, shift soff, mirror m) at the lags lag0 + d, d < ND, for
 // the image staged in img; red holds 4 ND doubles.  Reduction in a fixed
@@ -439,12 +440,108 @@ __device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* 
   __syncthreads();
 }
 
+// The same FP32 CC for NC candidates (ref k[c], mirror m[c], shift soff[c])
+// at the lags lag0[c] + d, d < 3, evaluated together: each ring's stencil is
+// loaded once per mirror that occurs (MIXED: both occur) and serves every
+// candidate of that mirror, and the NC * 3 sums share one reduction (red
+// holds 12 NC doubles).  Every sum takes the arithmetic of rescore_lags<3> in
+// the same order, so the values are bit-identical to evaluating the
+// candidates one at a time.  The ring loop is unrolled so that about as many
+// loads are in flight for every NC.
+template <int NC, bool MIXED>
+__device__ __forceinline__ void rescore_group(const RescoreArgs& a, const float* img, double* red, const int* k,
+                                              const int* m, const int* soff, const int* lag0, double (&out)[NC][3]) {
+  const int base = (a.cx + a.pad) * a.Lp + (a.cx + a.pad);
+  const int j = threadIdx.x;
+  const int jm = (kNphi - j) & 255;
+  // unmixed: every candidate's mirror is m[0]
+  const Stencil* st0 = a.stencil + (MIXED ? j : (m[0] ? jm : j));
+  const Stencil* st1 = a.stencil + jm;
+  float acc[NC][3];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc[c][d] = 0.f;
+#pragma unroll(NC == 1 ? 8 : (NC == 2 ? 4 : (NC == 3 ? 3 : 2)))
+  for (int r = 0; r < a.R; ++r) {
+    const Stencil s0 = st0[r * kNphi];
+    Stencil s1 = s0;
+    if constexpr (MIXED) s1 = st1[r * kNphi];
+    const float w = (float)(a.r_min + r);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const Stencil st = (MIXED && m[c]) ? s1 : s0;
+      const float p = bilin(img, base + st.dy * a.Lp + (st.bx >> 2) + soff[c], a.Lp, st.fx, st.fy);
+      const float* q = a.qhat + ((size_t)k[c] * a.R + r) * kNphi;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc[c][d] += w * (p * q[(j + lag0[c] + d) & 255]);
+    }
+  }
+  // the reduction of rescore_lags, for every sum
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double v = (double)acc[c][d];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if ((j & 63) == 0) red[(c * 3 + d) * 4 + (j >> 6)] = v;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double* r4 = red + (c * 3 + d) * 4;
+      out[c][d] = ((r4[0] + r4[1]) + r4[2]) + r4[3];
+    }
+  __syncthreads();
+}
+
+// Candidates t0 .. t0 + nc - 1 (nc <= 4) of the list cand (flat indices):
+// their FP32 values at the three lags around each one's angle, folded into
+// (best, best_i) in list order (ties: the smallest flat index).
+template <int NC>
+__device__ __forceinline__ void rescore_fold(const RescoreArgs& a, const float* img, double* red, const int* cand,
+                                             float& best, int& best_i) {
+  int k[NC], m[NC], soff[NC], lag0[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int idx = __builtin_amdgcn_readfirstlane(cand[c]);  // the same in every lane
+    const int ang = idx & 255;
+    int rest = idx >> 8;
+    const int s = rest % a.S;
+    rest /= a.S;
+    m[c] = rest % a.M;
+    k[c] = rest / a.M;
+    soff[c] = (s / a.S1 - a.T) * a.Lp + (s % a.S1 - a.T);
+    lag0[c] = (ang + 255) & 255;
+  }
+  bool mixed = false;  // workgroup-uniform
+#pragma unroll
+  for (int c = 1; c < NC; ++c) mixed |= m[c] != m[0];
+  double v[NC][3];
+  if (mixed)
+    rescore_group<NC, true>(a, img, red, k, m, soff, lag0, v);
+  else
+    rescore_group<NC, false>(a, img, red, k, m, soff, lag0, v);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int i2 = (__builtin_amdgcn_readfirstlane(cand[c]) & ~255) | ((lag0[c] + d) & 255);
+      const float f = (float)v[c][d];
+      if (f > best || (f == best && i2 < best_i)) {
+        best = f;
+        best_i = i2;
+      }
+    }
+}
+
 __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, float* smem) {
   float* img = smem;
   double* red = reinterpret_cast<double*>(smem + ((a.Lp * a.Lp + 1) & ~1));
-  int* cand = reinterpret_cast<int*>(red + 16);  // candidate rows' flat indices
-  float* rv = reinterpret_cast<float*>(cand + kMaxRescoreRows);  // the particle's row results
-  int* ri = reinterpret_cast<int*>(rv + kMaxRows);
+  int* cand = reinterpret_cast<int*>(red + kRescoreRed);  // candidate rows' flat indices
   const int64_t gi = a.out_off + n;
   stage_image(img, a.parts + (size_t)n * a.L * a.L, a.L, a.Lp, a.pad);
   if (a.rows <= 1) {
@@ -460,62 +557,65 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
     if (threadIdx.x == 0) a.cc[gi] = (float)v[0];
     return;
   }
-  // the a.rows best rows of the 16-bit pass (thread 0, from LDS; S is at
-  // most 289)
-  for (int s = threadIdx.x; s < a.S; s += 256) {
-    rv[s] = a.row_cc[(size_t)n * a.S + s];
-    ri[s] = a.row_idx[(size_t)n * a.S + s];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float bv[kMaxRescoreRows];
-    int bi[kMaxRescoreRows];
+  // the a.rows best rows of the 16-bit pass, by wave 0: lane l holds rows
+  // l + 64 i, and each round takes the largest (value, then smallest flat
+  // index) of the rows not yet taken across the wave.  Rows without a
+  // candidate (index 2^31 - 1) and NaN values never count.
+  if (threadIdx.x < 64) {
+    constexpr int kPer = (kMaxRows + 63) / 64;
+    const int l = threadIdx.x;
+    float lv[kPer];
+    int li[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int s = l + 64 * e;
+      lv[e] = s < a.S ? a.row_cc[(size_t)n * a.S + s] : -INFINITY;
+      li[e] = s < a.S ? a.row_idx[(size_t)n * a.S + s] : 0x7fffffff;
+      if (lv[e] != lv[e]) li[e] = 0x7fffffff;
+    }
     const int nr = a.rows < kMaxRescoreRows ? a.rows : kMaxRescoreRows;
-    for (int i = 0; i < nr; ++i) {
-      bv[i] = -INFINITY;
-      bi[i] = 0x7fffffff;
-    }
-    for (int s = 0; s < a.S; ++s) {
-      float v = rv[s];
-      int i = ri[s];
-      if (i == 0x7fffffff) continue;
-      for (int t = 0; t < nr; ++t)  // insertion into the sorted list
-        if (v > bv[t] || (v == bv[t] && i < bi[t])) {
-          const float tv = bv[t];
-          const int ti = bi[t];
-          bv[t] = v;
-          bi[t] = i;
-          v = tv;
-          i = ti;
+    float top = -INFINITY;
+    for (int t = 0; t < kMaxRescoreRows; ++t) {
+      float bv = -INFINITY;
+      int bi = 0x7fffffff;
+      if (t < nr) {  // uniform
+#pragma unroll
+        for (int e = 0; e < kPer; ++e)
+          if (li[e] != 0x7fffffff && (lv[e] > bv || (lv[e] == bv && li[e] < bi))) {
+            bv = lv[e];
+            bi = li[e];
+          }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const float ov = __shfl_xor(bv, o);
+          const int oi = __shfl_xor(bi, o);
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
         }
+#pragma unroll
+        for (int e = 0; e < kPer; ++e)
+          if (li[e] == bi) li[e] = 0x7fffffff;  // taken (flat indices are distinct)
+      }
+      if (t == 0) top = bv;
+      // only rows within the re-ranking margin of the particle's best are
+      // candidates; pruning keeps their bests exact
+      const float lim = top > -INFINITY ? top - a.margin * fabsf(top) : top;
+      if (l == 0) cand[t] = (t < nr && bv >= lim) ? bi : 0x7fffffff;
     }
-    // only rows within the re-ranking margin of the particle's best (bv[0])
-    // are candidates; pruning keeps their bests exact
-    const float lim = bv[0] > -INFINITY ? bv[0] - a.margin * fabsf(bv[0]) : bv[0];
-    for (int t = 0; t < kMaxRescoreRows; ++t) cand[t] = (t < nr && bv[t] >= lim) ? bi[t] : 0x7fffffff;
   }
   __syncthreads();
+  int nc = 0;  // the candidates form a prefix of the list (values descend)
+  while (nc < kMaxRescoreRows && __builtin_amdgcn_readfirstlane(cand[nc]) != 0x7fffffff) ++nc;
   float best = -INFINITY;
   int best_i = 0x7fffffff;
-  for (int t = 0; t < kMaxRescoreRows; ++t) {
-    const int idx = cand[t];  // uniform
-    if (idx == 0x7fffffff) break;
-    const int ang = idx & 255;
-    int rest = idx >> 8;
-    const int s = rest % a.S;
-    rest /= a.S;
-    const int m = rest % a.M, k = rest / a.M;
-    const int sx = s % a.S1 - a.T, sy = s / a.S1 - a.T;
-    double v[3];
-    rescore_lags<3>(a, img, red, k, m, sy * a.Lp + sx, (ang + 255) & 255, v);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int i2 = (idx & ~255) | ((ang + 255 + d) & 255);
-      const float f = (float)v[d];
-      if (f > best || (f == best && i2 < best_i)) {
-        best = f;
-        best_i = i2;
-      }
+  for (int t0 = 0; t0 < nc; t0 += 4) {  // workgroup-uniform
+    switch (nc - t0 < 4 ? nc - t0 : 4) {
+      case 1: rescore_fold<1>(a, img, red, cand + t0, best, best_i); break;
+      case 2: rescore_fold<2>(a, img, red, cand + t0, best, best_i); break;
+      case 3: rescore_fold<3>(a, img, red, cand + t0, best, best_i); break;
+      default: rescore_fold<4>(a, img, red, cand + t0, best, best_i); break;
     }
   }
   if (threadIdx.x != 0) return;
@@ -539,8 +639,8 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
 }
 
 static size_t rescore_lds_bytes(int Lp) {
-  return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + 16 * sizeof(double) + kMaxRescoreRows * sizeof(int) +
-         kMaxRows * (sizeof(float) + sizeof(int));
+  return (size_t)((Lp * Lp + 1) & ~1) * sizeof(float) + kRescoreRed * sizeof(double) +
+         kMaxRescoreRows * sizeof(int);
 }
 
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs a) {
