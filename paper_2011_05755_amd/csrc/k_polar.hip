@@ -394,7 +394,7 @@ hipError_t launch_polar(int mode, const PolarArgs& a, hipStream_t st) {
 // best below it are left out (they cannot win at 16-bit accuracy).
 constexpr int kMaxRescoreRows = 8;
 constexpr int kMaxRows = 289;  // shifts per particle at the largest search range (+-8)
-constexpr int kRescoreRed = 48;  // reduction slots: 4 waves x 3 lags x up to 4 candidates
+constexpr int kRescoreRed = 24;  // reduction slots: 4 waves x 3 lags x up to 2 candidates
 
 // FP32 CC of (ref k, shift soff, mirror m) at the lags lag0 + d, d < ND, for
 // the image staged in img; red holds 4 ND doubles.  Reduction in a fixed
@@ -446,8 +446,9 @@ __device__ __forceinline__ void rescore_lags(const RescoreArgs& a, const float* 
 // candidate of that mirror, and the NC * 3 sums share one reduction (red
 // holds 12 NC doubles).  Every sum takes the arithmetic of rescore_lags<3> in
 // the same order, so the values are bit-identical to evaluating the
-// candidates one at a time.  The ring loop is unrolled so that about as many
-// loads are in flight for every NC.
+// candidates one at a time.  The unroll keeps either form within 80
+// registers, six workgroups per CU (the four-candidate form needs 117, and
+// its occupancy costs more than the shared loads save).
 template <int NC, bool MIXED>
 __device__ __forceinline__ void rescore_group(const RescoreArgs& a, const float* img, double* red, const int* k,
                                               const int* m, const int* soff, const int* lag0, double (&out)[NC][3]) {
@@ -462,7 +463,9 @@ __device__ __forceinline__ void rescore_group(const RescoreArgs& a, const float*
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int d = 0; d < 3; ++d) acc[c][d] = 0.f;
-#pragma unroll(NC == 1 ? 8 : (NC == 2 ? 4 : (NC == 3 ? 3 : 2)))
+  static_assert(NC * 12 <= kRescoreRed, "reduction slots");
+  constexpr int kUnroll = NC == 1 ? 8 : 2;
+#pragma unroll kUnroll
   for (int r = 0; r < a.R; ++r) {
     const Stencil s0 = st0[r * kNphi];
     Stencil s1 = s0;
@@ -498,7 +501,7 @@ __device__ __forceinline__ void rescore_group(const RescoreArgs& a, const float*
   __syncthreads();
 }
 
-// Candidates t0 .. t0 + nc - 1 (nc <= 4) of the list cand (flat indices):
+// Candidates cand[0 .. NC - 1] (flat indices, NC <= 2):
 // their FP32 values at the three lags around each one's angle, folded into
 // (best, best_i) in list order (ties: the smallest flat index).
 template <int NC>
@@ -610,13 +613,11 @@ __device__ __forceinline__ void rescore_particle(const RescoreArgs& a, int n, fl
   while (nc < kMaxRescoreRows && __builtin_amdgcn_readfirstlane(cand[nc]) != 0x7fffffff) ++nc;
   float best = -INFINITY;
   int best_i = 0x7fffffff;
-  for (int t0 = 0; t0 < nc; t0 += 4) {  // workgroup-uniform
-    switch (nc - t0 < 4 ? nc - t0 : 4) {
-      case 1: rescore_fold<1>(a, img, red, cand + t0, best, best_i); break;
-      case 2: rescore_fold<2>(a, img, red, cand + t0, best, best_i); break;
-      case 3: rescore_fold<3>(a, img, red, cand + t0, best, best_i); break;
-      default: rescore_fold<4>(a, img, red, cand + t0, best, best_i); break;
-    }
+  for (int t0 = 0; t0 < nc; t0 += 2) {  // workgroup-uniform
+    if (nc - t0 == 1)
+      rescore_fold<1>(a, img, red, cand + t0, best, best_i);
+    else
+      rescore_fold<2>(a, img, red, cand + t0, best, best_i);
   }
   if (threadIdx.x != 0) return;
   if (best_i == 0x7fffffff) {  // the 16-bit pass found no candidate: keep its (invalid) result
