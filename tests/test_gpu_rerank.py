@@ -74,6 +74,51 @@ def test_reranked_winner_is_never_worse_and_reports_its_fp32_cc(ctx, form):
     log(f"{form}: oracle parameters matched {same[1]} -> {same[4]} of {len(c1)} with 4-row re-ranking")
 
 
+def mirror_symmetric(parts, L):
+    """Each image made symmetric about the mirror axis, the horizontal line
+    through the sampling centre (row L // 2): rows y and L - y averaged, row 0
+    (whose partner lies outside the box, where images are zero) cleared."""
+    c = L // 2
+    ys = torch.arange(1, L)
+    p = parts.clone()
+    p[:, 1:, :] = 0.5 * (parts[:, ys, :] + parts[:, 2 * c - ys, :])
+    p[:, 0, :] = 0
+    return p
+
+
+@pytest.mark.parametrize("form", ["bf16", "fp16"])
+def test_mirror_symmetric_particles_rerank_candidates_of_both_mirrors(ctx, form):
+    """Particles symmetric about the mirror axis: every mirrored row ties with
+    the unmirrored row at the opposite vertical shift, so a particle's best
+    rows come in pairs of both mirrors and the re-ranking evaluates candidates
+    of both mirrors side by side.  Each reported CC is still the oracle's CC of
+    the reported candidate, and the re-ranked winner is never worse."""
+    refs, parts, g = case(99, N=48)
+    sym = mirror_symmetric(parts, g.L)
+    table = oracle.cc_table(sym.numpy(), refs.numpy(), g)   # [N, K, M, S1 (sy), S1 (sx), 256]
+    want = oracle.align(sym.numpy(), refs.numpy(), g)
+    scale = np.abs(want["cc"])
+    # the construction: mirror 1 at (sx, sy) equals mirror 0 at (sx, -sy)
+    np.testing.assert_allclose(table[:, :, 1], table[:, :, 0, ::-1], rtol=0, atol=1e-9 * scale.max())
+    got = {}
+    for rows in (1, 4):
+        ctx.load_refs(94, refs.to(DEV), r_min=1, r_max=30, shift_max=g.shift_max, precision=form,
+                      rescore_rows=rows)
+        got[rows] = ctx.align(94, sym.to(DEV), with_cc2=True).to_numpy()
+    for rows, res in got.items():
+        tcc = oracle_cc_of(table, res, g)
+        assert (np.abs(res["cc"] - tcc) / scale).max() <= 1e-5, rows
+    # the GPU sees the tie too: the best candidate other than the winner (its
+    # mirror partner) is within the 16-bit tolerance of the winner
+    assert np.all(np.abs(got[4]["cc2"] - got[4]["cc"]) <= 2e-3 * scale)
+    c1, c4 = oracle_cc_of(table, got[1], g), oracle_cc_of(table, got[4], g)
+    assert np.all(c4 >= c1 - 2e-5 * scale)
+    best = {r: int(np.sum(np.abs(oracle_cc_of(table, got[r], g) - want["cc"]) <= 2e-5 * scale)) for r in got}
+    assert best[4] >= best[1]
+    log(f"{form} symmetric: oracle's best CC reached {best[1]} -> {best[4]} of {len(c1)}; "
+        f"mirror 1 reported for {int(np.sum(got[4]['mirror']))}")
+
+
 def test_rescore_rows_one_is_the_plain_rescore_and_batch_matches(ctx):
     from paper_2011_05755_amd import mra
     refs, parts, g = case(96, N=37)
